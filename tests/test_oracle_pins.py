@@ -1,0 +1,412 @@
+"""Pins of the FP64 oracle to facts other than its own code.
+
+Each test ties one oracle routine to something the mathematics or the
+physics fixes: hand-derived closed forms (tests/golden), a 40-digit decimal
+brute force, the potential whose negative gradient the acceleration must be,
+an independent NumPy form shaped like the paper's broadcasting listing
+(section 3.1), conservation laws and orbit closed forms for the integrator,
+and central finite differences / torch autograd for the derivatives.
+"""
+import math
+import os
+from decimal import Decimal, getcontext
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2203_08263_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _abs_force_sum(pos, mass, G, eps):
+    """sum_j |G m_j d_ij| s_ij^-3/2 per target i (scale for error bounds)."""
+    d = pos[:, None, :] - pos[:, :, None]          # d[c, i, j] = x_j - x_i
+    s = (d ** 2).sum(axis=0) + eps * eps
+    return G * (mass[None, :] * np.sqrt((d ** 2).sum(axis=0)) * s ** -1.5).sum(axis=1)
+
+
+# ----------------------------------------------------------------- forward --
+
+def test_golden_two_body_closed_form(oracle):
+    vals = {}
+    with open(os.path.join(GOLDEN, "two_body_pythagorean.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            key, *rest = line.split()
+            vals[key] = [float(Fraction(t)) for t in rest]
+    G, eps = vals["G"][0], math.sqrt(vals["eps2"][0])
+    pos = np.array([vals["x1"], vals["x2"]]).T.copy()
+    mass = np.array(vals["m"])
+    a = oracle.accel(pos, mass, G, eps)
+    np.testing.assert_allclose(a[:, 0], vals["a1"], rtol=4e-16, atol=1e-300)
+    np.testing.assert_allclose(a[:, 1], vals["a2"], rtol=4e-16, atol=1e-300)
+    kin, pot = oracle.energy(pos, np.zeros((3, 2)), mass, G, eps)
+    assert kin == 0.0
+    assert abs(pot - vals["W"][0]) <= 4e-16
+
+
+def _decimal_accel(pos, mass, G, eps):
+    getcontext().prec = 40
+    n = mass.size
+    P = [[Decimal(float(pos[c, i])) for i in range(n)] for c in range(3)]
+    M = [Decimal(float(m)) for m in mass]
+    e2 = Decimal(float(eps)) * Decimal(float(eps))
+    out = np.zeros((3, n))
+    for i in range(n):
+        acc = [Decimal(0)] * 3
+        for j in range(n):
+            d = [P[c][j] - P[c][i] for c in range(3)]
+            s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + e2
+            w = M[j] / (s * s.sqrt())
+            acc = [acc[c] + w * d[c] for c in range(3)]
+        for c in range(3):
+            out[c, i] = float(Decimal(float(G)) * acc[c])
+    return out
+
+
+@pytest.mark.parametrize("seed,n,eps", [(1, 7, 1e-3), (2, 5, 0.3), (3, 8, 1e-2)])
+def test_accel_vs_decimal_bruteforce(oracle, seed, n, eps):
+    rng = _rng(seed)
+    pos = rng.uniform(-1, 1, (3, n))
+    mass = rng.uniform(0.5, 1.0, n) / n
+    a = oracle.accel(pos, mass, 1.0, eps)
+    ref = _decimal_accel(pos, mass, 1.0, eps)
+    bound = 8 * np.finfo(float).eps * _abs_force_sum(pos, mass, 1.0, eps)
+    assert np.all(np.abs(a - ref) <= bound[None, :])
+
+
+def _decimal_potential(pos, mass, G, eps):
+    getcontext().prec = 40
+    n = mass.size
+    e2 = Decimal(float(eps)) ** 2
+    W = Decimal(0)
+    for i in range(n):
+        for j in range(i + 1, n):
+            s = sum((Decimal(float(pos[c, j])) - Decimal(float(pos[c, i]))) ** 2
+                    for c in range(3)) + e2
+            W -= Decimal(float(mass[i])) * Decimal(float(mass[j])) / s.sqrt()
+    return float(Decimal(float(G)) * W)
+
+
+def test_potential_vs_decimal(oracle):
+    rng = _rng(11)
+    pos = rng.uniform(-1, 1, (3, 9))
+    mass = rng.uniform(0.5, 1.0, 9)
+    _, pot = oracle.energy(pos, np.zeros((3, 9)), mass, 1.0, 0.05)
+    ref = _decimal_potential(pos, mass, 1.0, 0.05)
+    assert abs(pot - ref) <= 1e-14 * abs(ref)
+
+
+def test_kinetic_energy_closed_form(oracle):
+    vel = np.array([[1.0, 0.0], [2.0, -3.0], [2.0, 0.5]])
+    mass = np.array([2.0, 4.0])
+    kin, _ = oracle.energy(np.zeros((3, 2)) + np.arange(2)[None, :], vel, mass, 1.0, 0.1)
+    assert kin == pytest.approx(0.5 * 2.0 * 9.0 + 0.5 * 4.0 * 9.25, rel=1e-15)
+
+
+def test_accel_is_minus_gradient_of_potential(oracle):
+    # m_i a_i = -dW/dx_i for the Plummer-softened potential W; central
+    # differences of the oracle's potential (a separate formula) pin the
+    # sign, the power -3/2, eps^2 and G of the force at once.
+    rng = _rng(5)
+    n, G, eps = 6, 1.7, 0.2
+    pos = rng.uniform(-1, 1, (3, n))
+    mass = rng.uniform(0.5, 1.0, n)
+    vel = np.zeros((3, n))
+    a = oracle.accel(pos, mass, G, eps)
+    h = 1e-5
+    for i in range(n):
+        for c in range(3):
+            xp, xm = pos.copy(), pos.copy()
+            xp[c, i] += h
+            xm[c, i] -= h
+            dW = (oracle.energy(xp, vel, mass, G, eps)[1]
+                  - oracle.energy(xm, vel, mass, G, eps)[1]) / (2 * h)
+            assert mass[i] * a[c, i] == pytest.approx(-dW, rel=1e-7, abs=1e-9)
+
+
+def _numpy_broadcast_accel(pos, mass, G, eps):
+    """Independent form shaped like the paper's CPython broadcasting listing
+    (section 3.1): per target i, vectorised over sources, force G m_i m_j
+    d s^-1.5 summed, then divided by m_i.  AoS (n, 3) layout."""
+    P = pos.T.copy()
+    soft = eps * eps
+    out = np.empty_like(P)
+    for i in range(P.shape[0]):
+        dpos = np.subtract(P, P[i])
+        dsq = (dpos ** 2.0).sum(axis=1) + soft
+        gm = mass * (mass[i] * G)
+        forces = np.multiply((gm * dsq ** -1.5).reshape(-1, 1), dpos).sum(axis=0)
+        out[i] = forces / mass[i]
+    return out.T
+
+
+def test_accel_vs_numpy_broadcasting_form(oracle):
+    pos, _, mass = inputs.uniform_cube(400, 77)
+    a = oracle.accel(pos, mass, 1.0, 1e-3)
+    ref = _numpy_broadcast_accel(pos, mass, 1.0, 1e-3)
+    bound = 64 * np.finfo(float).eps * _abs_force_sum(pos, mass, 1.0, 1e-3)
+    assert np.all(np.abs(a - ref) <= bound[None, :])
+
+
+def test_shell_theorem_uniform_ball(oracle):
+    # Far outside a ball of total mass M the field is that of a point mass;
+    # well inside a homogeneous ball it is -G M r / R^3.  Loose (sampling)
+    # check of the force law's overall scale and sign at large N.
+    rng = _rng(9)
+    n = 20000
+    u = rng.normal(size=(3, n))
+    u /= np.linalg.norm(u, axis=0)
+    r = rng.uniform(0, 1, n) ** (1.0 / 3.0)
+    pos = u * r
+    mass = np.full(n, 1.0 / n)
+    # 2048 probes on a sphere of radius 5 (outside) and 2048 at radius 0.3
+    # (inside); the mean radial field averages out discreteness noise, and a
+    # softening of 0.02 (about half the mean spacing) tames close encounters.
+    k = 2048
+    dirs = rng.normal(size=(3, k))
+    dirs /= np.linalg.norm(dirs, axis=0)
+    probes = np.concatenate([5.0 * dirs, 0.3 * dirs], axis=1)
+    pos2 = np.concatenate([pos, probes], axis=1)
+    mass2 = np.concatenate([mass, np.zeros(2 * k)])
+    a = oracle.accel_rows(pos2, mass2, 1.0, 2e-2, np.arange(n, n + 2 * k))
+    radial = (a * np.concatenate([dirs, dirs], axis=1)).sum(axis=0)
+    # Gauss: the sphere-averaged radial field is -G M_enc / r^2.
+    m_in = mass[np.linalg.norm(pos, axis=0) < 0.3].sum()
+    assert radial[:k].mean() == pytest.approx(-1.0 / 25.0, rel=1e-2)
+    assert radial[k:].mean() == pytest.approx(-m_in / 0.09, rel=2e-2)
+
+
+def test_single_body_and_self_term(oracle):
+    a = oracle.accel(np.array([[0.3], [-0.2], [0.9]]), np.array([5.0]), 1.0, 1e-3)
+    assert np.all(a == 0.0)
+
+
+def test_newton_third_law(oracle):
+    pos, _, mass = inputs.uniform_cube(500, 3)
+    a = oracle.accel(pos, mass, 1.0, 1e-3)
+    net = (mass[None, :] * a).sum(axis=1)
+    scale = (mass * _abs_force_sum(pos, mass, 1.0, 1e-3)).sum()
+    assert np.all(np.abs(net) <= 1e-13 * scale)
+
+
+def test_exact_scaling_and_reflection(oracle):
+    pos, _, mass = inputs.uniform_cube(200, 4)
+    a = oracle.accel(pos, mass, 1.0, 1e-3)
+    assert np.array_equal(oracle.accel(-pos, mass, 1.0, 1e-3), -a)
+    assert np.array_equal(oracle.accel(pos, 2 * mass, 1.0, 1e-3), 2 * a)
+    assert np.array_equal(oracle.accel(2 * pos, mass, 1.0, 2e-3), a / 4)
+    assert np.array_equal(oracle.accel(pos, mass, 4.0, 1e-3), 4 * a)
+
+
+def test_permutation_equivariance(oracle):
+    pos, _, mass = inputs.uniform_cube(300, 6)
+    perm = _rng(1).permutation(300)
+    a = oracle.accel(pos, mass, 1.0, 1e-3)
+    ap = oracle.accel(pos[:, perm], mass[perm], 1.0, 1e-3)
+    bound = 64 * np.finfo(float).eps * _abs_force_sum(pos, mass, 1.0, 1e-3)
+    assert np.all(np.abs(ap - a[:, perm]) <= bound[perm][None, :])
+
+
+def test_accel_rows_bitwise(oracle):
+    pos, _, mass = inputs.uniform_cube(257, 8)
+    rows = inputs.subset_rows(257, 40, 3)
+    assert np.array_equal(oracle.accel_rows(pos, mass, 1.0, 1e-3, rows),
+                          oracle.accel(pos, mass, 1.0, 1e-3)[:, rows])
+
+
+# -------------------------------------------------------------- integrator --
+
+def _circular_two_body(m1, m2, R, eps, G):
+    w = math.sqrt(G * (m1 + m2) / (R * R + eps * eps) ** 1.5)
+    r1, r2 = R * m2 / (m1 + m2), R * m1 / (m1 + m2)
+    pos = np.array([[-r1, r2], [0.0, 0.0], [0.0, 0.0]])
+    vel = np.array([[0.0, 0.0], [-w * r1, w * r2], [0.0, 0.0]])
+    return pos, vel, np.array([m1, m2]), w, r1, r2
+
+
+def test_two_body_circular_orbit(oracle):
+    # Circular orbit of two softened bodies about their centre of mass with
+    # omega^2 = G (m1+m2) / (R^2+eps^2)^(3/2).  Leapfrog's phase error grows
+    # as dt^2, so halving dt must cut the position error by ~4x.
+    m1, m2, R, eps, G = 1.0, 0.5, 1.0, 0.3, 1.0
+    errs = []
+    for nsteps in (400, 800):
+        pos, vel, mass, w, r1, r2 = _circular_two_body(m1, m2, R, eps, G)
+        T = 2 * math.pi / w
+        x, v, _ = oracle.step(pos, vel, mass, G, eps, T / nsteps, nsteps)
+        errs.append(np.abs(x - pos).max())
+        # radius about the COM is conserved by symmetry of the orbit
+        assert np.hypot(x[0, 0], x[1, 0]) == pytest.approx(r1, rel=1e-4)
+    assert errs[0] < 1e-3
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_energy_drift_second_order(oracle):
+    pos, vel, mass = inputs.uniform_cube(64, 21)
+    eps, T = 0.1, 0.5
+    drift = []
+    for dt in (1e-2, 5e-3):
+        x, v, _ = oracle.step(pos, vel, mass, 1.0, eps, dt, int(round(T / dt)))
+        e0 = sum(oracle.energy(pos, vel, mass, 1.0, eps))
+        e1 = sum(oracle.energy(x, v, mass, 1.0, eps))
+        drift.append(abs(e1 - e0) / abs(e0))
+    assert drift[0] < 1e-5
+    assert 3.0 < drift[0] / drift[1] < 5.0
+
+
+def test_momentum_conserved(oracle):
+    pos, vel, mass = inputs.uniform_cube(128, 22)
+    x, v, _ = oracle.step(pos, vel, mass, 1.0, 1e-3, 1e-3, 50)
+    p0, p1 = oracle.momentum(vel, mass), oracle.momentum(v, mass)
+    assert np.all(np.abs(p1 - p0) <= 1e-14 * (mass * np.abs(vel).sum(0)).sum() * 50)
+
+
+def test_time_reversibility(oracle):
+    pos, vel, mass = inputs.uniform_cube(64, 23)
+    x, v, a = oracle.step(pos, vel, mass, 1.0, 0.05, 1e-3, 40)
+    xb, vb, _ = oracle.step(x, -v, mass, 1.0, 0.05, 1e-3, 40, acc=a)
+    assert np.abs(xb - pos).max() < 1e-12
+    assert np.abs(-vb - vel).max() < 1e-11
+
+
+def test_step_chaining_bitwise(oracle):
+    pos, vel, mass = inputs.uniform_cube(96, 24)
+    x1, v1, a1 = oracle.step(pos, vel, mass, 1.0, 1e-3, 1e-3, 7)
+    x2, v2, a2 = oracle.step(x1, v1, mass, 1.0, 1e-3, 1e-3, 5, acc=a1)
+    x3, v3, a3 = oracle.step(pos, vel, mass, 1.0, 1e-3, 1e-3, 12)
+    assert np.array_equal(x2, x3) and np.array_equal(v2, v3) and np.array_equal(a2, a3)
+
+
+def test_zero_steps_fills_acc(oracle):
+    pos, vel, mass = inputs.uniform_cube(32, 25)
+    x, v, a = oracle.step(pos, vel, mass, 1.0, 1e-3, 1e-3, 0)
+    assert np.array_equal(x, pos) and np.array_equal(v, vel)
+    assert np.array_equal(a, oracle.accel(pos, mass, 1.0, 1e-3))
+
+
+# --------------------------------------------------------------------- VJP --
+
+def _central_fd(f, z, h):
+    g = np.zeros_like(z)
+    for idx in np.ndindex(z.shape):
+        zp, zm = z.copy(), z.copy()
+        zp[idx] += h
+        zm[idx] -= h
+        g[idx] = (f(zp) - f(zm)) / (2 * h)
+    return g
+
+
+def test_vjp_central_fd(oracle):
+    rng = _rng(31)
+    n, G, eps = 10, 1.3, 0.15
+    pos = rng.uniform(-1, 1, (3, n))
+    mass = rng.uniform(0.5, 1.0, n)
+    gbar = rng.normal(size=(3, n))
+    gp, gm = oracle.accel_vjp(pos, mass, gbar, G, eps)
+    L_x = lambda x: float((gbar * oracle.accel(x, mass, G, eps)).sum())
+    L_m = lambda m: float((gbar * oracle.accel(pos, m, G, eps)).sum())
+    np.testing.assert_allclose(gp, _central_fd(L_x, pos, 1e-6), rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(gm, _central_fd(L_m, mass, 1e-6), rtol=1e-6, atol=1e-7)
+
+
+def test_vjp_vs_torch_autograd(oracle):
+    torch = pytest.importorskip("torch")
+    rng = _rng(32)
+    n, G, eps = 16, 1.0, 0.01
+    pos = rng.uniform(-1, 1, (3, n))
+    mass = rng.uniform(0.5, 1.0, n) / n
+    gbar = rng.normal(size=(3, n))
+    X = torch.tensor(pos, dtype=torch.float64, requires_grad=True)
+    M = torch.tensor(mass, dtype=torch.float64, requires_grad=True)
+    d = X[:, None, :] - X[:, :, None]                 # d[c, i, j] = x_j - x_i
+    s = (d * d).sum(0) + eps * eps
+    a = G * (M[None, None, :] * d * s[None] ** -1.5).sum(-1)
+    a.backward(torch.tensor(gbar))
+    gp, gm = oracle.accel_vjp(pos, mass, gbar, G, eps)
+    scale = np.abs(X.grad.numpy()).max()
+    np.testing.assert_allclose(gp, X.grad.numpy(), rtol=1e-11, atol=1e-12 * scale)
+    np.testing.assert_allclose(gm, M.grad.numpy(), rtol=1e-11,
+                               atol=1e-12 * np.abs(M.grad.numpy()).max())
+
+
+def test_vjp_invariants(oracle):
+    pos, _, mass = inputs.uniform_cube(200, 33)
+    gbar = inputs.upstream_normal(200, 34)
+    gp, gm = oracle.accel_vjp(pos, mass, gbar, 1.0, 1e-3)
+    a = oracle.accel(pos, mass, 1.0, 1e-3)
+    # translation invariance of a: sum_k dL/dx_k = 0
+    assert np.all(np.abs(gp.sum(axis=1)) <= 1e-11 * np.abs(gp).sum(axis=1))
+    # a is linear in the masses: sum_j m_j dL/dm_j = <gbar, a>
+    lhs, rhs = float((mass * gm).sum()), float((gbar * a).sum())
+    assert lhs == pytest.approx(rhs, rel=1e-11)
+
+
+def test_vjp_rows_bitwise(oracle):
+    pos, _, mass = inputs.uniform_cube(129, 35)
+    gbar = inputs.upstream_normal(129, 36)
+    rows = inputs.subset_rows(129, 17, 1)
+    gp, gm = oracle.accel_vjp(pos, mass, gbar, 1.0, 1e-3)
+    gpr, gmr = oracle.accel_vjp_rows(pos, mass, gbar, 1.0, 1e-3, rows)
+    assert np.array_equal(gpr, gp[:, rows]) and np.array_equal(gmr, gm[rows])
+
+
+# ---------------------------------------------------------------- adjoint --
+
+def test_step_adjoint_central_fd(oracle):
+    rng = _rng(41)
+    n, G, eps, dt, S = 6, 1.0, 0.2, 0.02, 9
+    pos = rng.uniform(-1, 1, (3, n))
+    vel = rng.normal(0, 0.3, (3, n))
+    mass = rng.uniform(0.5, 1.0, n)
+    cx, cv = rng.normal(size=(3, n)), rng.normal(size=(3, n))
+
+    def loss(x0, v0, m):
+        x, v, _ = oracle.step(x0, v0, m, G, eps, dt, S)
+        return float((cx * x).sum() + (cv * v).sum() + 0.5 * (x * x).sum())
+
+    xS, vS, _ = oracle.step(pos, vel, mass, G, eps, dt, S)
+    gx, gv, gm = oracle.step_adjoint(pos, vel, mass, G, eps, dt, S, cx + xS, cv)
+    h = 1e-6
+    np.testing.assert_allclose(gx, _central_fd(lambda z: loss(z, vel, mass), pos, h),
+                               rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(gv, _central_fd(lambda z: loss(pos, z, mass), vel, h),
+                               rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(gm, _central_fd(lambda z: loss(pos, vel, z), mass, h),
+                               rtol=1e-6, atol=1e-7)
+
+
+def test_step_adjoint_with_gacc_fd(oracle):
+    # dL/da_S enters through a_S = A(x_S); check against FD of <c, a_S>.
+    rng = _rng(42)
+    n, G, eps, dt, S = 5, 1.0, 0.25, 0.03, 4
+    pos = rng.uniform(-1, 1, (3, n))
+    vel = rng.normal(0, 0.3, (3, n))
+    mass = rng.uniform(0.5, 1.0, n)
+    ca = rng.normal(size=(3, n))
+
+    def loss(v0):
+        _, _, a = oracle.step(pos, v0, mass, G, eps, dt, S)
+        return float((ca * a).sum())
+
+    z = np.zeros((3, n))
+    _, gv, _ = oracle.step_adjoint(pos, vel, mass, G, eps, dt, S, z, z, gacc_T=ca)
+    np.testing.assert_allclose(gv, _central_fd(loss, vel, 1e-6), rtol=1e-6, atol=1e-7)
+
+
+def test_step_adjoint_zero_steps_is_vjp(oracle):
+    pos, vel, mass = inputs.uniform_cube(40, 43)
+    gx = inputs.upstream_normal(40, 44)
+    gv = inputs.upstream_normal(40, 45)
+    ga = inputs.upstream_normal(40, 46)
+    ox, ov, om = oracle.step_adjoint(pos, vel, mass, 1.0, 1e-3, 1e-3, 0, gx, gv, ga)
+    vp, vm = oracle.accel_vjp(pos, mass, ga, 1.0, 1e-3)
+    assert np.array_equal(ov, gv)
+    assert np.array_equal(ox, gx + vp) and np.array_equal(om, vm)
