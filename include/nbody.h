@@ -1,0 +1,206 @@
+/*
+ * nbody.h -- C ABI of the MI355X (gfx950) all-pairs gravitational N-body
+ * library libnbody_hip.so.
+ *
+ * The operation is the direct-summation N-body problem of arxiv 2203.08263,
+ * section 2.3 (every body feels the Newtonian pull of every other body; no
+ * body moves until all forces of the step are summed, and no body starts the
+ * next step before the current one ends), with the force loop of the
+ * section 3.2 / 3.3 listings and the 20-flop-per-pair convention of
+ * section 4.1.  The paper gives no values for G, the softening or the time
+ * step; they are call parameters here.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Layout: structure of arrays, component-major.  A "vector" argument is
+ *    one pointer to 3*n doubles {x_0..x_{n-1}, y_0..y_{n-1}, z_0..z_{n-1}}
+ *    (the paper keeps one contiguous 1-D array per coordinate, section 3.2
+ *    "arrays with simple data types" and the typed signature of section 3.3);
+ *    a "scalar" argument is n doubles.  n is the row stride.
+ *  - Memory: every array pointer is a DEVICE pointer (hipMalloc'd or from a
+ *    torch tensor on the same device), 8-byte aligned, unless the comment
+ *    says "host".  The caller owns all buffers, including the workspace and
+ *    checkpoint buffers; the library never allocates or frees device memory
+ *    and keeps no device state between calls.  Input and output arrays of one
+ *    call must not overlap unless the comment says "in/out".
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  All work
+ *    is enqueued on it and the call returns without synchronising; a fault
+ *    inside a kernel surfaces at the caller's next synchronisation.
+ *  - Errors: every int-returning call returns an nbody_status.  Argument
+ *    errors are detected on the host before anything is enqueued; on any
+ *    error nothing has been written.  nbody_last_error() gives a message for
+ *    the calling thread's most recent failure.  No call prints, throws or
+ *    exits.
+ *  - Determinism: no atomics are used; every sum is taken in a fixed order
+ *    that depends only on (n, precision).  Repeated calls with the same
+ *    inputs give bitwise identical results.
+ *  - Interactions: one force evaluation visits all n*n ordered pairs,
+ *    including j == i, whose contribution is exactly zero since eps > 0.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Physical constants of a call.  eps is the Plummer softening length: eps^2
+ * is added to |x_j - x_i|^2 (the paper's softening constant, added to the
+ * squared distance in the section 3.1-3.3 force loops).  dt is the time step
+ * (ignored by nbody_accel / nbody_accel_vjp).  Passed by host pointer. */
+typedef struct nbody_params {
+  double G;
+  double eps;
+  double dt;
+} nbody_params;
+
+/* Arithmetic of the pair force.  State, accumulation across source tiles,
+ * the integrator and every output are FP64 in all three.
+ *  NBODY_FP64       every operation in FP64.
+ *  NBODY_MIXED      positions and masses rounded to FP32; pair difference,
+ *                   r^2 + eps^2, reciprocal square root, cube and the
+ *                   multiply-adds in FP32; FP32 partial sums over chunks of
+ *                   32 sources are added into FP64 per-body accumulators.
+ *  NBODY_MIXED_D64  as NBODY_MIXED, but the coordinate difference x_j - x_i
+ *                   is taken in FP64 and rounded once to FP32, removing the
+ *                   error of rounding each position to FP32 first. */
+enum nbody_precision {
+  NBODY_FP64 = 0,
+  NBODY_MIXED = 1,
+  NBODY_MIXED_D64 = 2
+};
+
+enum nbody_status {
+  NBODY_OK = 0,
+  NBODY_ERR_INVALID_ARGUMENT = 1,
+  NBODY_ERR_WORKSPACE_TOO_SMALL = 2,
+  NBODY_ERR_HIP = 3,
+  NBODY_ERR_UNSUPPORTED = 4
+};
+
+/* nbody_step flag: `acc` already holds A(pos), skip the initial evaluation.
+ * Chaining nbody_step(a steps) then nbody_step(b steps, NBODY_ACC_VALID) is
+ * bitwise identical to nbody_step(a + b steps). */
+#define NBODY_ACC_VALID 1u
+
+/* Operation selector for nbody_workspace_bytes. */
+enum nbody_op {
+  NBODY_OP_ACCEL = 0,
+  NBODY_OP_STEP = 1,
+  NBODY_OP_VJP = 2,
+  NBODY_OP_STEP_ADJOINT = 3
+};
+
+/* Largest supported body count. */
+#define NBODY_MAX_N ((int64_t)1 << 28)
+
+/* Workspace (device scratch) bytes that `op` needs for these arguments; 0 if
+ * none is needed, and (size_t)-1 if the arguments are invalid.  steps and
+ * ckpt_every only matter for NBODY_OP_STEP_ADJOINT. */
+size_t nbody_workspace_bytes(int op, int64_t n, int64_t steps,
+                             int64_t ckpt_every, int precision);
+
+/* Bytes of the checkpoint buffer nbody_step fills and nbody_step_adjoint
+ * reads: max(1, ceil(steps / ckpt_every)) records of 9*n doubles, record c
+ * holding x, v, a (three vectors) at step c*ckpt_every.  (size_t)-1 if the
+ * arguments are invalid. */
+size_t nbody_checkpoint_bytes(int64_t n, int64_t steps, int64_t ckpt_every);
+
+/* All-pairs softened acceleration (section 2.3; force loop of sections
+ * 3.1-3.3):
+ *     a_i = G * sum_{j=0}^{n-1} m_j (x_j - x_i) (|x_j - x_i|^2 + eps^2)^(-3/2)
+ *  pos  [vector] in    body positions
+ *  mass [scalar] in    body masses
+ *  acc  [vector] out   accelerations
+ *  p    host     in    G (finite), eps (finite, > 0); dt unused
+ *  ws   device   scratch of ws_bytes >= nbody_workspace_bytes(NBODY_OP_ACCEL)
+ *                (may be NULL when that is 0)
+ * Errors: INVALID_ARGUMENT (n outside [1, NBODY_MAX_N], NULL pointer,
+ * non-finite G/eps, eps <= 0, unknown precision, misaligned pointer),
+ * WORKSPACE_TOO_SMALL, HIP (launch failure; see nbody_last_error). */
+int nbody_accel(int64_t n, const double *pos, const double *mass, double *acc,
+                const nbody_params *p, int precision, void *ws,
+                size_t ws_bytes, void *stream);
+
+/* `steps` kick-drift-kick leapfrog steps, in place (the paper's step loop of
+ * section 2.3 with its two dependencies; the integrator is KDK):
+ *     v += (dt/2) a;  x += dt v;  a = A(x);  v += (dt/2) a
+ * one force evaluation per step.
+ *  pos  [vector] in/out  positions x_0 -> x_steps
+ *  vel  [vector] in/out  velocities v_0 -> v_steps
+ *  acc  [vector] in/out  in: A(x_0) if flags has NBODY_ACC_VALID (otherwise
+ *                        ignored and computed first); out: A(x_steps)
+ *  mass [scalar] in
+ *  p    host     in      G, eps as nbody_accel; dt finite
+ *  flags                 0 or NBODY_ACC_VALID
+ *  ckpt device   out     nullable.  If given, ckpt_every >= 1 and it must
+ *                        hold nbody_checkpoint_bytes(n, steps, ckpt_every)
+ *                        bytes; record c receives (x, v, a) at step
+ *                        c*ckpt_every, as nbody_step_adjoint needs them.
+ *  ws   device           >= nbody_workspace_bytes(NBODY_OP_STEP)
+ * steps == 0 is a no-op that still fills acc when NBODY_ACC_VALID is absent.
+ * Errors: as nbody_accel, plus steps < 0, ckpt_every < 1 with ckpt, unknown
+ * flag bits, non-finite dt. */
+int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
+               double *acc, const double *mass, const nbody_params *p,
+               int precision, unsigned flags, double *ckpt,
+               int64_t ckpt_every, void *ws, size_t ws_bytes, void *stream);
+
+/* Vector-Jacobian product of nbody_accel (the exact derivative of the
+ * section 2.3 force sum; the paper itself has no derivative).  Given
+ * gbar = dL/da, with e_kj = x_j - x_k, s = |e_kj|^2 + eps^2 and
+ * h_kj = m_k gbar_j - m_j gbar_k:
+ *     dL/dm_k = -G sum_j (gbar_j . e_kj) s^(-3/2)
+ *     dL/dx_k =  G sum_j [ s^(-3/2) h_kj - 3 s^(-5/2) (e_kj . h_kj) e_kj ]
+ * Each output row k is owned by one thread (no scatter).
+ *  pos, mass     in    as nbody_accel
+ *  gacc [vector] in    dL/da
+ *  gpos [vector] out   dL/dx (overwritten, not accumulated)
+ *  gmass[scalar] out   dL/dm (overwritten)
+ *  ws            >= nbody_workspace_bytes(NBODY_OP_VJP)
+ * Errors: as nbody_accel. */
+int nbody_accel_vjp(int64_t n, const double *pos, const double *mass,
+                    const double *gacc, double *gpos, double *gmass,
+                    const nbody_params *p, int precision, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* Reverse sweep of nbody_step (called without NBODY_ACC_VALID, or with a
+ * valid acc = A(x_0)): gradients of L(x_S, v_S, a_S) with respect to x_0,
+ * v_0 and the masses.  Uses the checkpoints nbody_step wrote with the same
+ * n, steps, ckpt_every, p and precision; each segment of ckpt_every steps is
+ * recomputed from its checkpoint with the forward's own kernels (bitwise the
+ * same trajectory), then walked backwards:
+ *     abar += (dt/2) vbar;  (xbar, mbar) += VJP(x_{t+1}; abar);
+ *     vbar += dt xbar;      abar = (dt/2) vbar
+ * ending with (xbar, mbar) += VJP(x_0; abar).
+ *  ckpt  device in     checkpoint buffer from nbody_step
+ *  mass  [scalar] in
+ *  gpos  [vector] in/out  in: dL/dx_S   out: dL/dx_0
+ *  gvel  [vector] in/out  in: dL/dv_S   out: dL/dv_0
+ *  gacc_T[vector] in      nullable: dL/da_S (taken as 0 when NULL)
+ *  gmass [scalar] out     dL/dm (overwritten)
+ *  ws             >= nbody_workspace_bytes(NBODY_OP_STEP_ADJOINT, n, steps,
+ *                    ckpt_every, precision)
+ * steps == 0 gives gpos += VJP_x(x_0; gacc_T), gmass = VJP_m(x_0; gacc_T)
+ * (gvel unchanged), reading x_0 from checkpoint record 0.
+ * Errors: as nbody_step; ckpt_every must be >= 1. */
+int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
+                       const double *ckpt, const double *mass,
+                       const nbody_params *p, int precision, double *gpos,
+                       double *gvel, const double *gacc_T, double *gmass,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* Static description of a status code (never NULL). */
+const char *nbody_error_string(int code);
+
+/* Message for the calling thread's most recent failing call ("" if none). */
+const char *nbody_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

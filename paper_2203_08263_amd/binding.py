@@ -1,0 +1,261 @@
+"""ctypes binding of libnbody_hip.so (C ABI in include/nbody.h).
+
+Argument marshalling only: every function checks torch tensors (float64,
+contiguous, on the current HIP device, component-major ``(3, n)`` vectors
+and ``(n,)`` masses), allocates the workspace the library asks for from
+torch's caching allocator, and passes raw device pointers plus the current
+torch stream.  All arithmetic happens in the library's gfx950 kernels.  The
+names mirror the C entry points.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libnbody_hip.so")
+
+NBODY_FP64 = 0
+NBODY_MIXED = 1
+NBODY_MIXED_D64 = 2
+PRECISIONS = {"fp64": NBODY_FP64, "mixed": NBODY_MIXED,
+              "mixed_d64": NBODY_MIXED_D64}
+
+NBODY_OK = 0
+NBODY_ACC_VALID = 1
+NBODY_OP_ACCEL, NBODY_OP_STEP, NBODY_OP_VJP, NBODY_OP_STEP_ADJOINT = 0, 1, 2, 3
+NBODY_MAX_N = 1 << 28
+
+SYMBOLS = ("nbody_workspace_bytes", "nbody_checkpoint_bytes", "nbody_accel",
+           "nbody_step", "nbody_accel_vjp", "nbody_step_adjoint",
+           "nbody_error_string", "nbody_last_error")
+
+_INVALID = ctypes.c_size_t(-1).value
+
+
+class NBodyError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("nbody error %d: %s" % (code, message))
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_double), ("eps", ctypes.c_double),
+                ("dt", ctypes.c_double)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(
+            "libnbody_hip.so is not built (%s); run "
+            "`python -m paper_2203_08263_amd.build` -- there is no CPU "
+            "fallback" % _LIB_PATH)
+    lib = ctypes.CDLL(_LIB_PATH)
+    i64, sz, vp, ci = ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int
+    pp = ctypes.POINTER(_Params)
+    lib.nbody_workspace_bytes.argtypes = [ci, i64, i64, i64, ci]
+    lib.nbody_workspace_bytes.restype = sz
+    lib.nbody_checkpoint_bytes.argtypes = [i64, i64, i64]
+    lib.nbody_checkpoint_bytes.restype = sz
+    lib.nbody_accel.argtypes = [i64, vp, vp, vp, pp, ci, vp, sz, vp]
+    lib.nbody_step.argtypes = [i64, i64, vp, vp, vp, vp, pp, ci, ctypes.c_uint,
+                               vp, i64, vp, sz, vp]
+    lib.nbody_accel_vjp.argtypes = [i64, vp, vp, vp, vp, vp, pp, ci, vp, sz, vp]
+    lib.nbody_step_adjoint.argtypes = [i64, i64, i64, vp, vp, pp, ci, vp, vp,
+                                       vp, vp, vp, sz, vp]
+    for f in ("nbody_accel", "nbody_step", "nbody_accel_vjp",
+              "nbody_step_adjoint"):
+        getattr(lib, f).restype = ci
+    lib.nbody_error_string.argtypes = [ci]
+    lib.nbody_error_string.restype = ctypes.c_char_p
+    lib.nbody_last_error.argtypes = []
+    lib.nbody_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != NBODY_OK:
+        lib = load_library()
+        raise NBodyError(rc, lib.nbody_last_error().decode() or
+                         lib.nbody_error_string(rc).decode())
+
+
+def _precision(p) -> int:
+    if isinstance(p, str):
+        if p not in PRECISIONS:
+            raise ValueError("unknown precision %r" % p)
+        return PRECISIONS[p]
+    return int(p)
+
+
+def _vec(t, n, name, device=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != torch.float64 or t.shape != (3, n) or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous float64 (3, %d) tensor, got "
+                         "%s %s" % (name, n, t.dtype, tuple(t.shape)))
+    if t.device.type != "cuda" or (device is not None and t.device != device):
+        raise ValueError("%s must be on the GPU device %s" % (name, device))
+    return t
+
+
+def _scal(t, n, name, device=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != torch.float64 or t.shape != (n,) or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous float64 (%d,) tensor" % (name, n))
+    if t.device.type != "cuda" or (device is not None and t.device != device):
+        raise ValueError("%s must be on the GPU device %s" % (name, device))
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _workspace(nbytes, device, workspace=None):
+    if nbytes == _INVALID:
+        raise NBodyError(1, "invalid arguments for the workspace size")
+    if nbytes == 0:
+        return None, 0
+    if workspace is not None:
+        if workspace.device != device or not workspace.is_contiguous():
+            raise ValueError("workspace must be contiguous on %s" % device)
+        if workspace.numel() * workspace.element_size() < nbytes:
+            raise ValueError("workspace smaller than the %d bytes needed" % nbytes)
+        return workspace, workspace.numel() * workspace.element_size()
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    return ws, nbytes
+
+
+def nbody_workspace_bytes(op: int, n: int, steps: int = 0, ckpt_every: int = 1,
+                          precision=NBODY_FP64) -> int:
+    return int(load_library().nbody_workspace_bytes(op, n, steps, ckpt_every,
+                                                    _precision(precision)))
+
+
+def nbody_checkpoint_bytes(n: int, steps: int, ckpt_every: int) -> int:
+    return int(load_library().nbody_checkpoint_bytes(n, steps, ckpt_every))
+
+
+def nbody_accel(pos, mass, G=1.0, eps=1e-3, precision=NBODY_FP64, out=None,
+                workspace=None):
+    """Accelerations (3, n) of all bodies (all-pairs, softened)."""
+    lib = load_library()
+    n = mass.shape[0]
+    dev = mass.device
+    _scal(mass, n, "mass")
+    _vec(pos, n, "pos", dev)
+    prec = _precision(precision)
+    acc = torch.empty((3, n), dtype=torch.float64, device=dev) if out is None \
+        else _vec(out, n, "out", dev)
+    ws, wsb = _workspace(lib.nbody_workspace_bytes(NBODY_OP_ACCEL, n, 0, 1, prec),
+                         dev, workspace)
+    prm = _Params(G, eps, 0.0)
+    _check(lib.nbody_accel(n, _ptr(pos), _ptr(mass), _ptr(acc), ctypes.byref(prm),
+                           prec, _ptr(ws), wsb, _stream(dev)))
+    return acc
+
+
+def nbody_step(pos, vel, acc, mass, G=1.0, eps=1e-3, dt=1e-3, steps=1,
+               precision=NBODY_FP64, acc_valid=False, ckpt=None, ckpt_every=0,
+               workspace=None):
+    """`steps` KDK leapfrog steps in place on pos, vel, acc."""
+    lib = load_library()
+    n = mass.shape[0]
+    dev = mass.device
+    _scal(mass, n, "mass")
+    _vec(pos, n, "pos", dev)
+    _vec(vel, n, "vel", dev)
+    _vec(acc, n, "acc", dev)
+    prec = _precision(precision)
+    if ckpt is not None:
+        need = lib.nbody_checkpoint_bytes(n, steps, ckpt_every)
+        if need == _INVALID:
+            raise NBodyError(1, "invalid checkpoint arguments")
+        if (ckpt.dtype != torch.float64 or not ckpt.is_contiguous()
+                or ckpt.device != dev or ckpt.numel() * 8 < need):
+            raise ValueError("ckpt must be contiguous float64 on %s with at "
+                             "least %d bytes" % (dev, need))
+    ws, wsb = _workspace(lib.nbody_workspace_bytes(NBODY_OP_STEP, n, steps, 1, prec),
+                         dev, workspace)
+    prm = _Params(G, eps, dt)
+    flags = NBODY_ACC_VALID if acc_valid else 0
+    _check(lib.nbody_step(n, int(steps), _ptr(pos), _ptr(vel), _ptr(acc),
+                          _ptr(mass), ctypes.byref(prm), prec, flags, _ptr(ckpt),
+                          int(ckpt_every), _ptr(ws), wsb, _stream(dev)))
+    return pos, vel, acc
+
+
+def nbody_accel_vjp(pos, mass, gacc, G=1.0, eps=1e-3, precision=NBODY_FP64,
+                    gpos=None, gmass=None, workspace=None):
+    """(dL/dx (3, n), dL/dm (n,)) for upstream gacc = dL/da."""
+    lib = load_library()
+    n = mass.shape[0]
+    dev = mass.device
+    _scal(mass, n, "mass")
+    _vec(pos, n, "pos", dev)
+    _vec(gacc, n, "gacc", dev)
+    prec = _precision(precision)
+    gpos = torch.empty((3, n), dtype=torch.float64, device=dev) if gpos is None \
+        else _vec(gpos, n, "gpos", dev)
+    gmass = torch.empty(n, dtype=torch.float64, device=dev) if gmass is None \
+        else _scal(gmass, n, "gmass", dev)
+    ws, wsb = _workspace(lib.nbody_workspace_bytes(NBODY_OP_VJP, n, 0, 1, prec),
+                         dev, workspace)
+    prm = _Params(G, eps, 0.0)
+    _check(lib.nbody_accel_vjp(n, _ptr(pos), _ptr(mass), _ptr(gacc), _ptr(gpos),
+                               _ptr(gmass), ctypes.byref(prm), prec, _ptr(ws),
+                               wsb, _stream(dev)))
+    return gpos, gmass
+
+
+def nbody_step_adjoint(ckpt, mass, gpos, gvel, G=1.0, eps=1e-3, dt=1e-3,
+                       steps=1, ckpt_every=1, precision=NBODY_FP64,
+                       gacc_T=None, gmass=None, workspace=None):
+    """Reverse sweep: gpos/gvel (in: dL/dx_S, dL/dv_S) become dL/dx_0, dL/dv_0
+    in place; returns (gpos, gvel, gmass)."""
+    lib = load_library()
+    n = mass.shape[0]
+    dev = mass.device
+    _scal(mass, n, "mass")
+    _vec(gpos, n, "gpos", dev)
+    _vec(gvel, n, "gvel", dev)
+    if gacc_T is not None:
+        _vec(gacc_T, n, "gacc_T", dev)
+    prec = _precision(precision)
+    need = lib.nbody_checkpoint_bytes(n, steps, ckpt_every)
+    if need == _INVALID:
+        raise NBodyError(1, "invalid checkpoint arguments")
+    if (ckpt.dtype != torch.float64 or not ckpt.is_contiguous()
+            or ckpt.device != dev or ckpt.numel() * 8 < need):
+        raise ValueError("ckpt must be contiguous float64 on %s with at least "
+                         "%d bytes" % (dev, need))
+    gmass = torch.empty(n, dtype=torch.float64, device=dev) if gmass is None \
+        else _scal(gmass, n, "gmass", dev)
+    ws, wsb = _workspace(lib.nbody_workspace_bytes(NBODY_OP_STEP_ADJOINT, n, steps,
+                                                   ckpt_every, prec), dev, workspace)
+    prm = _Params(G, eps, dt)
+    _check(lib.nbody_step_adjoint(n, int(steps), int(ckpt_every), _ptr(ckpt),
+                                  _ptr(mass), ctypes.byref(prm), prec, _ptr(gpos),
+                                  _ptr(gvel), _ptr(gacc_T), _ptr(gmass), _ptr(ws),
+                                  wsb, _stream(dev)))
+    return gpos, gvel, gmass

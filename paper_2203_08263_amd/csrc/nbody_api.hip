@@ -1,0 +1,368 @@
+// C ABI of libnbody_hip.so: argument validation, workspace carving, the
+// kick-drift-kick step loop and the checkpointed reverse sweep.  All device
+// work is enqueued on the caller's stream; nothing here allocates device
+// memory or synchronises.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "../../include/nbody.h"
+#include "nbody_internal.h"
+
+using nbody::Plan;
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+  return fail(NBODY_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+constexpr size_t kInvalid = (size_t)-1;
+
+size_t round_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+size_t dbytes(int64_t count) { return round_up(size_t(count) * sizeof(double)); }
+
+bool valid_precision(int p) {
+  return p == NBODY_FP64 || p == NBODY_MIXED || p == NBODY_MIXED_D64;
+}
+
+bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+int check_common(int64_t n, const nbody_params *p, int precision,
+                 bool need_dt) {
+  if (n < 1 || n > NBODY_MAX_N)
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "n = %lld outside [1, %lld]",
+                (long long)n, (long long)NBODY_MAX_N);
+  if (!p) return fail(NBODY_ERR_INVALID_ARGUMENT, "params pointer is NULL");
+  if (!isfinite(p->G))
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "G is not finite");
+  if (!isfinite(p->eps) || !(p->eps > 0.0))
+    return fail(NBODY_ERR_INVALID_ARGUMENT,
+                "eps must be finite and > 0 (the j == i term needs it)");
+  if (!(p->eps * p->eps > 0.0) || !isfinite(p->eps * p->eps))
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "eps^2 underflows or overflows");
+  if (need_dt && !isfinite(p->dt))
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "dt is not finite");
+  if (!valid_precision(precision))
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "unknown precision %d", precision);
+  return NBODY_OK;
+}
+
+int check_ptr(const void *ptr, const char *name) {
+  if (!ptr) return fail(NBODY_ERR_INVALID_ARGUMENT, "%s is NULL", name);
+  if (!aligned8(ptr))
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "%s is not 8-byte aligned", name);
+  return NBODY_OK;
+}
+
+int check_ws(void *ws, size_t ws_bytes, size_t need) {
+  if (need == 0) return NBODY_OK;
+  if (ws_bytes < need)
+    return fail(NBODY_ERR_WORKSPACE_TOO_SMALL,
+                "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  if (!ws) return fail(NBODY_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (!aligned8(ws))
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "workspace is not 8-byte aligned");
+  return NBODY_OK;
+}
+
+// Workspace sizes of each operation (see the layouts in the entry points).
+size_t ws_accel(int64_t n, int prec) {
+  const Plan pl = nbody::make_plan(nbody::kAccel, prec, n);
+  return pl.sj > 1 ? dbytes(pl.sj * 3 * n) : 0;
+}
+size_t ws_step(int64_t n, int prec) {
+  const Plan pl = nbody::make_plan(nbody::kAccel, prec, n);
+  return dbytes(pl.sj * 3 * n);
+}
+size_t ws_vjp(int64_t n, int prec) {
+  const Plan pl = nbody::make_plan(nbody::kVjp, prec, n);
+  return pl.sj > 1 ? dbytes(pl.sj * 4 * n) : 0;
+}
+size_t ws_part_adjoint(int64_t n, int prec) {
+  const Plan pf = nbody::make_plan(nbody::kAccel, prec, n);
+  const Plan pv = nbody::make_plan(nbody::kVjp, prec, n);
+  return std::max(dbytes(pf.sj * 3 * n), dbytes(pv.sj * 4 * n));
+}
+size_t ws_adjoint(int64_t n, int64_t steps, int64_t K, int prec) {
+  const int64_t seg = std::min<int64_t>(K, std::max<int64_t>(steps, 1));
+  // v, a, abar, segment positions, partial sums
+  return 3 * dbytes(3 * n) + dbytes(seg * 3 * n) + ws_part_adjoint(n, prec);
+}
+
+int64_t num_records(int64_t steps, int64_t K) {
+  return std::max<int64_t>(1, (steps + K - 1) / K);
+}
+
+// One force evaluation into partial sums (unscaled; G is applied by the
+// consumer) -- the form the step loop and the recomputation share.
+int accel_to_parts(const Plan &pl, int prec, int n, const double *pos,
+                   const double *mass, double eps2, double *part,
+                   hipStream_t st) {
+  hipError_t e = nbody::launch_accel(pl, prec, n, pos, mass, eps2, 1.0, part,
+                                     size_t(3) * n, st);
+  return e == hipSuccess ? NBODY_OK : hip_fail(e, "accel kernel launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nbody_error_string(int code) {
+  switch (code) {
+    case NBODY_OK: return "success";
+    case NBODY_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case NBODY_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case NBODY_ERR_HIP: return "HIP runtime error";
+    case NBODY_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status code";
+}
+
+const char *nbody_last_error(void) { return g_last_error; }
+
+size_t nbody_workspace_bytes(int op, int64_t n, int64_t steps,
+                             int64_t ckpt_every, int precision) {
+  if (n < 1 || n > NBODY_MAX_N || !valid_precision(precision)) return kInvalid;
+  switch (op) {
+    case NBODY_OP_ACCEL: return ws_accel(n, precision);
+    case NBODY_OP_STEP: return ws_step(n, precision);
+    case NBODY_OP_VJP: return ws_vjp(n, precision);
+    case NBODY_OP_STEP_ADJOINT:
+      if (steps < 0 || ckpt_every < 1) return kInvalid;
+      return ws_adjoint(n, steps, ckpt_every, precision);
+  }
+  return kInvalid;
+}
+
+size_t nbody_checkpoint_bytes(int64_t n, int64_t steps, int64_t ckpt_every) {
+  if (n < 1 || n > NBODY_MAX_N || steps < 0 || ckpt_every < 1) return kInvalid;
+  return size_t(num_records(steps, ckpt_every)) * 9 * size_t(n) *
+         sizeof(double);
+}
+
+int nbody_accel(int64_t n, const double *pos, const double *mass, double *acc,
+                const nbody_params *p, int precision, void *ws,
+                size_t ws_bytes, void *stream) {
+  int rc;
+  if ((rc = check_common(n, p, precision, false))) return rc;
+  if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(mass, "mass")) ||
+      (rc = check_ptr(acc, "acc")))
+    return rc;
+  if ((rc = check_ws(ws, ws_bytes, ws_accel(n, precision)))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nn = int(n);
+  const double eps2 = p->eps * p->eps;
+  const Plan pl = nbody::make_plan(nbody::kAccel, precision, n);
+  hipError_t e;
+  if (pl.sj == 1) {
+    e = nbody::launch_accel(pl, precision, nn, pos, mass, eps2, p->G, acc, 0,
+                            st);
+    if (e != hipSuccess) return hip_fail(e, "accel kernel launch");
+    return NBODY_OK;
+  }
+  double *part = static_cast<double *>(ws);
+  if ((rc = accel_to_parts(pl, precision, nn, pos, mass, eps2, part, st)))
+    return rc;
+  e = nbody::launch_reduce(nn, int(pl.sj), part, size_t(3) * n, p->G, acc,
+                           nullptr, st);
+  return e == hipSuccess ? NBODY_OK : hip_fail(e, "reduce kernel launch");
+}
+
+int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
+               double *acc, const double *mass, const nbody_params *p,
+               int precision, unsigned flags, double *ckpt,
+               int64_t ckpt_every, void *ws, size_t ws_bytes, void *stream) {
+  int rc;
+  if ((rc = check_common(n, p, precision, true))) return rc;
+  if (steps < 0)
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "steps = %lld < 0",
+                (long long)steps);
+  if (flags & ~NBODY_ACC_VALID)
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x",
+                flags & ~NBODY_ACC_VALID);
+  if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(vel, "vel")) ||
+      (rc = check_ptr(acc, "acc")) || (rc = check_ptr(mass, "mass")))
+    return rc;
+  if (ckpt) {
+    if (ckpt_every < 1)
+      return fail(NBODY_ERR_INVALID_ARGUMENT,
+                  "ckpt_every = %lld < 1 with a checkpoint buffer",
+                  (long long)ckpt_every);
+    if ((rc = check_ptr(ckpt, "ckpt"))) return rc;
+  }
+  if ((rc = check_ws(ws, ws_bytes, ws_step(n, precision)))) return rc;
+
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nn = int(n);
+  const double eps2 = p->eps * p->eps, G = p->G, dt = p->dt, h = 0.5 * dt;
+  const Plan pl = nbody::make_plan(nbody::kAccel, precision, n);
+  double *part = static_cast<double *>(ws);
+  const size_t stride = size_t(3) * n;
+  const size_t rec_len = size_t(9) * n;
+  hipError_t e;
+
+  // Step 0: a_0 (computed or given), checkpoint record 0, opening half-kick
+  // and drift.
+  const bool have_acc = flags & NBODY_ACC_VALID;
+  if (!have_acc) {
+    if ((rc = accel_to_parts(pl, precision, nn, pos, mass, eps2, part, st)))
+      return rc;
+  }
+  if (!have_acc || ckpt || steps > 0) {
+    e = nbody::launch_update(nn, int(pl.sj), have_acc ? nullptr : part, stride,
+                             G, acc, have_acc ? nullptr : acc, pos, pos, vel,
+                             vel, h, dt, ckpt,
+                             steps > 0 ? unsigned(nbody::kOpen) : 0u, st);
+    if (e != hipSuccess) return hip_fail(e, "update kernel launch");
+  }
+  for (int64_t t = 0; t < steps; ++t) {
+    if ((rc = accel_to_parts(pl, precision, nn, pos, mass, eps2, part, st)))
+      return rc;
+    const bool more = t + 1 < steps;
+    double *rec = nullptr;
+    if (ckpt && more && (t + 1) % ckpt_every == 0)
+      rec = ckpt + size_t((t + 1) / ckpt_every) * rec_len;
+    const unsigned fl = nbody::kClose | (more ? unsigned(nbody::kOpen) : 0u);
+    e = nbody::launch_update(nn, int(pl.sj), part, stride, G, nullptr, acc,
+                             pos, pos, vel, vel, h, dt, rec, fl, st);
+    if (e != hipSuccess) return hip_fail(e, "update kernel launch");
+  }
+  return NBODY_OK;
+}
+
+int nbody_accel_vjp(int64_t n, const double *pos, const double *mass,
+                    const double *gacc, double *gpos, double *gmass,
+                    const nbody_params *p, int precision, void *ws,
+                    size_t ws_bytes, void *stream) {
+  int rc;
+  if ((rc = check_common(n, p, precision, false))) return rc;
+  if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(mass, "mass")) ||
+      (rc = check_ptr(gacc, "gacc")) || (rc = check_ptr(gpos, "gpos")) ||
+      (rc = check_ptr(gmass, "gmass")))
+    return rc;
+  if ((rc = check_ws(ws, ws_bytes, ws_vjp(n, precision)))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nn = int(n);
+  const double eps2 = p->eps * p->eps;
+  const Plan pl = nbody::make_plan(nbody::kVjp, precision, n);
+  hipError_t e;
+  if (pl.sj == 1) {
+    e = nbody::launch_vjp(pl, precision, nn, pos, mass, gacc, eps2, p->G, gpos,
+                          gmass, 0, st);
+    return e == hipSuccess ? NBODY_OK : hip_fail(e, "vjp kernel launch");
+  }
+  double *part = static_cast<double *>(ws);
+  const size_t stride = size_t(4) * n;
+  e = nbody::launch_vjp(pl, precision, nn, pos, mass, gacc, eps2, 1.0, part,
+                        part + size_t(3) * n, stride, st);
+  if (e != hipSuccess) return hip_fail(e, "vjp kernel launch");
+  e = nbody::launch_reduce(nn, int(pl.sj), part, stride, p->G, gpos, gmass, st);
+  return e == hipSuccess ? NBODY_OK : hip_fail(e, "reduce kernel launch");
+}
+
+int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
+                       const double *ckpt, const double *mass,
+                       const nbody_params *p, int precision, double *gpos,
+                       double *gvel, const double *gacc_T, double *gmass,
+                       void *ws, size_t ws_bytes, void *stream) {
+  int rc;
+  if ((rc = check_common(n, p, precision, true))) return rc;
+  if (steps < 0)
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "steps = %lld < 0",
+                (long long)steps);
+  if (ckpt_every < 1)
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "ckpt_every = %lld < 1",
+                (long long)ckpt_every);
+  if ((rc = check_ptr(ckpt, "ckpt")) || (rc = check_ptr(mass, "mass")) ||
+      (rc = check_ptr(gpos, "gpos")) || (rc = check_ptr(gvel, "gvel")) ||
+      (rc = check_ptr(gmass, "gmass")))
+    return rc;
+  if (gacc_T && (rc = check_ptr(gacc_T, "gacc_T"))) return rc;
+  if ((rc = check_ws(ws, ws_bytes, ws_adjoint(n, steps, ckpt_every,
+                                              precision))))
+    return rc;
+
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nn = int(n);
+  const double eps2 = p->eps * p->eps, G = p->G, dt = p->dt, h = 0.5 * dt;
+  const Plan pf = nbody::make_plan(nbody::kAccel, precision, n);
+  const Plan pv = nbody::make_plan(nbody::kVjp, precision, n);
+  const size_t q3 = size_t(3) * n, rec_len = size_t(9) * n;
+  const int64_t seg_max = std::min<int64_t>(ckpt_every,
+                                            std::max<int64_t>(steps, 1));
+  // Workspace layout: v | a | abar | seg[seg_max] positions | partial sums.
+  char *w = static_cast<char *>(ws);
+  double *v_ws = reinterpret_cast<double *>(w);
+  w += dbytes(3 * n);
+  double *a_ws = reinterpret_cast<double *>(w);
+  w += dbytes(3 * n);
+  double *abar = reinterpret_cast<double *>(w);
+  w += dbytes(3 * n);
+  double *seg = reinterpret_cast<double *>(w);
+  w += dbytes(seg_max * 3 * n);
+  double *part = reinterpret_cast<double *>(w);
+  hipError_t e;
+
+  e = nbody::launch_adj_init(nn, gvel, gacc_T, h, steps > 0, abar, gmass, st);
+  if (e != hipSuccess) return hip_fail(e, "adjoint init launch");
+
+  const int64_t nrec = num_records(steps, ckpt_every);
+  for (int64_t c = (steps > 0 ? nrec - 1 : -1); c >= 0; --c) {
+    const int64_t s0 = c * ckpt_every;
+    const int64_t k = std::min<int64_t>(ckpt_every, steps - s0);
+    const double *rec = ckpt + size_t(c) * rec_len;
+    // Recompute x_{s0+1} .. x_{s0+k} from the checkpoint with the forward's
+    // own update and force kernels (bitwise the forward trajectory).
+    e = nbody::launch_update(nn, int(pf.sj), nullptr, q3, G, rec + 6 * n,
+                             nullptr, rec, seg, rec + 3 * n, v_ws, h, dt,
+                             nullptr, nbody::kOpen, st);
+    if (e != hipSuccess) return hip_fail(e, "update kernel launch");
+    for (int64_t t = 1; t < k; ++t) {
+      const double *xp = seg + size_t(t - 1) * q3;
+      if ((rc = accel_to_parts(pf, precision, nn, xp, mass, eps2, part, st)))
+        return rc;
+      e = nbody::launch_update(nn, int(pf.sj), part, q3, G, nullptr, a_ws, xp,
+                               seg + size_t(t) * q3, v_ws, v_ws, h, dt,
+                               nullptr, nbody::kClose | nbody::kOpen, st);
+      if (e != hipSuccess) return hip_fail(e, "update kernel launch");
+    }
+    // Reverse sweep over steps s0+k-1 .. s0: VJP at x_{t+1} = seg[t - s0].
+    for (int64_t t = s0 + k - 1; t >= s0; --t) {
+      const double *xt1 = seg + size_t(t - s0) * q3;
+      e = nbody::launch_vjp(pv, precision, nn, xt1, mass, abar, eps2, 1.0,
+                            part, part + q3, size_t(4) * n, st);
+      if (e != hipSuccess) return hip_fail(e, "vjp kernel launch");
+      e = nbody::launch_adj_combine(nn, int(pv.sj), part, size_t(4) * n, G, dt,
+                                    h, gpos, gvel, gmass, abar,
+                                    t > 0 ? nbody::kAdjMid : nbody::kAdjLast,
+                                    st);
+      if (e != hipSuccess) return hip_fail(e, "adjoint combine launch");
+    }
+  }
+  // a_0 = A(x_0): final VJP at the initial positions (checkpoint record 0).
+  e = nbody::launch_vjp(pv, precision, nn, ckpt, mass, abar, eps2, 1.0, part,
+                        part + q3, size_t(4) * n, st);
+  if (e != hipSuccess) return hip_fail(e, "vjp kernel launch");
+  e = nbody::launch_adj_combine(nn, int(pv.sj), part, size_t(4) * n, G, dt, h,
+                                gpos, gvel, gmass, abar, nbody::kAdjFinal, st);
+  if (e != hipSuccess) return hip_fail(e, "adjoint combine launch");
+  return NBODY_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// Internal interface between the C-ABI host layer (nbody_api.hip) and the
+// gfx950 kernels (nbody_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace nbody {
+
+// Threads per workgroup of every kernel (4 wave64s) and bodies per LDS tile.
+constexpr int kThreads = 256;
+
+// Launch plan of one all-pairs kernel: R target bodies per thread, n_ib
+// target blocks of kThreads*R bodies, sj source splits of jchunk bodies
+// (jchunk a multiple of kThreads).  Depends only on (kind, precision, n), so
+// a recomputation reproduces every partial sum bitwise.
+struct Plan {
+  int R;
+  int64_t n_ib;
+  int64_t sj;
+  int64_t jchunk;
+};
+
+enum KernelKind { kAccel = 0, kVjp = 1 };
+
+Plan make_plan(KernelKind kind, int precision, int64_t n);
+
+// out + s*split_stride + c*n + i  <-  scale * sum over source split s of the
+// acceleration sum (without G when scale == 1), c = 0..2.
+hipError_t launch_accel(const Plan &pl, int precision, int n, const double *pos,
+                        const double *mass, double eps2, double scale,
+                        double *out, size_t split_stride, hipStream_t st);
+
+// out_x + s*stride + c*n + i <- scale * sum_j [s^-3/2 h - 3 s^-5/2 (e.h) e],
+// out_m + s*stride + i       <- -scale * sum_j (gbar_j . e) s^-3/2.
+hipError_t launch_vjp(const Plan &pl, int precision, int n, const double *pos,
+                      const double *mass, const double *gacc, double eps2,
+                      double scale, double *out_x, double *out_m,
+                      size_t split_stride, hipStream_t st);
+
+// out_x[c*n+i] = G * sum_s part[s*stride + c*n + i], c < 3; if out_m:
+// out_m[i] = G * sum_s part[s*stride + 3*n + i].  Fixed ascending s order.
+hipError_t launch_reduce(int n, int sj, const double *part, size_t stride,
+                         double G, double *out_x, double *out_m,
+                         hipStream_t st);
+
+// Per-body state update of the kick-drift-kick loop (all FP64):
+//   a = part ? G * sum_s part[s] : a_in
+//   v = v_in;  if (close) v += h a            (closing half-kick)
+//   if (rec) rec <- (x_in, v, a)              (checkpoint record, 9n doubles)
+//   if (open) { v += h a; x_out = x_in + dt v }  (opening half-kick + drift)
+//   v_out = v;  if (acc_out) acc_out = a
+enum UpdateFlags { kClose = 1, kOpen = 2 };
+hipError_t launch_update(int n, int sj, const double *part, size_t stride,
+                         double G, const double *a_in, double *acc_out,
+                         const double *x_in, double *x_out, const double *v_in,
+                         double *v_out, double h, double dt, double *rec,
+                         unsigned flags, hipStream_t st);
+
+// Reverse sweep helpers (all FP64).
+//   abar = (gacc_T ? gacc_T : 0) + (add_hv ? h * gvel : 0);  gmass = 0
+hipError_t launch_adj_init(int n, const double *gvel, const double *gacc_T,
+                           double h, int add_hv, double *abar, double *gmass,
+                           hipStream_t st);
+//   gpos += G sum_s part_x;  gmass += G sum_s part_m
+//   mode kAdjMid:   gvel += dt gpos; abar = h gvel; abar += h gvel
+//   mode kAdjLast:  gvel += dt gpos; abar = h gvel
+//   mode kAdjFinal: nothing more
+enum AdjMode { kAdjMid = 0, kAdjLast = 1, kAdjFinal = 2 };
+hipError_t launch_adj_combine(int n, int sj, const double *part, size_t stride,
+                              double G, double dt, double h, double *gpos,
+                              double *gvel, double *gmass, double *abar,
+                              int mode, hipStream_t st);
+
+}  // namespace nbody

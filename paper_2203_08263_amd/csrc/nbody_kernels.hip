@@ -1,0 +1,566 @@
+// gfx950 kernels of the all-pairs gravitational N-body hot path.
+//
+// The all-pairs kernels (acceleration and its VJP) share one shape:
+//  - a workgroup of 256 threads (4 wave64s) owns kThreads*R target bodies,
+//    R per thread, strided by kThreads so every load and store is coalesced;
+//  - blockIdx.y selects a contiguous source range of jchunk bodies, staged
+//    through LDS in tiles of 256 bodies, one body loaded per thread from the
+//    structure-of-arrays FP64 state.  In the mixed modes the staging step is
+//    where positions and masses are rounded to FP32 (the "pack" of the source
+//    stream happens on the way into LDS, so no packed copy is ever written to
+//    HBM);
+//  - every thread walks the whole tile in ascending order reading each source
+//    body as a wave-uniform LDS broadcast, so one LDS read feeds 64*R pairs;
+//  - the tail of the last tile is padded with zero-mass bodies at the origin,
+//    whose contribution w*d with w = 0 is exactly zero;
+//  - each source split writes its own FP64 partial sum; the partials are
+//    added in ascending split order by the reduce / update kernels.  No
+//    atomics anywhere, so results are bitwise reproducible.
+//
+// The mixed modes sum FP32 pair terms over chunks of kChunk sources and add
+// each chunk into FP64 per-body accumulators.  The pair arithmetic is the
+// direct-summation force of arxiv 2203.08263 section 2.3 (force loop of the
+// section 3.2 / 3.3 listings) with the acceleration taken directly as
+// G sum_j m_j d s^-3/2 and the reciprocal square root from the hardware
+// approximation (v_rsq_f32 / v_rsq_f64), refined by Newton's method in FP64.
+#include "nbody_internal.h"
+#include "../../include/nbody.h"
+
+namespace nbody {
+namespace {
+
+constexpr int kChunk = 32;     // FP32 sources per FP64 flush (forward)
+constexpr int kVjpChunk = 16;  // FP32 sources per FP64 flush (VJP)
+
+// -------------------------------------------------------------- arithmetic --
+
+// 1/sqrt(s) in FP64: hardware estimate (about 23 correct bits) refined by two
+// Newton steps y <- y (3 - s y^2) / 2, written as y + y (1/2 - (s/2) y y).
+__device__ __forceinline__ double rsqrt_f64(double s) {
+  double y = __builtin_amdgcn_rsq(s);
+  const double hs = 0.5 * s;
+  double e = fma(-(hs * y), y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-(hs * y), y, 0.5);
+  y = fma(y, e, y);
+  return y;
+}
+
+__device__ __forceinline__ float rsqrt_f32(float s) {
+  return __builtin_amdgcn_rsqf(s);
+}
+
+// One source j acting on one target: a += m_j d (|d|^2 + eps^2)^-3/2.
+__device__ __forceinline__ void pair_f64(double dx, double dy, double dz,
+                                         double m, double eps2, double &ax,
+                                         double &ay, double &az) {
+  double s = fma(dx, dx, eps2);
+  s = fma(dy, dy, s);
+  s = fma(dz, dz, s);
+  const double y = rsqrt_f64(s);
+  const double w = (m * y) * (y * y);
+  ax = fma(w, dx, ax);
+  ay = fma(w, dy, ay);
+  az = fma(w, dz, az);
+}
+
+__device__ __forceinline__ void pair_f32(float dx, float dy, float dz, float m,
+                                         float eps2, float &ax, float &ay,
+                                         float &az) {
+  float s = fmaf(dx, dx, eps2);
+  s = fmaf(dy, dy, s);
+  s = fmaf(dz, dz, s);
+  const float y = rsqrt_f32(s);
+  const float w = (m * y) * (y * y);
+  ax = fmaf(w, dx, ax);
+  ay = fmaf(w, dy, ay);
+  az = fmaf(w, dz, az);
+}
+
+// h = a b - c d as the difference of two separately rounded products, so
+// that it is exactly antisymmetric under (a,b) <-> (c,d) and exactly zero for
+// the self pair j == k.  (A fused a*b - c*d leaves the rounding error of c*d,
+// which the self pair multiplies by eps^-3.)
+template <typename T>
+__device__ __forceinline__ T diff_of_products(T a, T b, T c, T d) {
+#pragma clang fp contract(off)
+  return a * b - c * d;
+}
+
+// One source j against target k for the VJP (row formulation):
+//   g += s^-3/2 (h + t e),  t = -3 (e.h) / s,   dm += (gbar_j . e) s^-3/2
+// with e = x_j - x_k and h = m_k gbar_j - m_j gbar_k.
+template <typename T>
+__device__ __forceinline__ void vjp_pair(T ex, T ey, T ez, T mj, T gjx, T gjy,
+                                         T gjz, T mk, T gkx, T gky, T gkz,
+                                         T eps2, T &gx, T &gy, T &gz, T &dm) {
+  T s = fma(ex, ex, eps2);
+  s = fma(ey, ey, s);
+  s = fma(ez, ez, s);
+  T y;
+  if constexpr (sizeof(T) == 8) y = rsqrt_f64(s); else y = rsqrt_f32(s);
+  const T y2 = y * y;
+  const T y3 = y2 * y;
+  const T hx = diff_of_products(mk, gjx, mj, gkx);
+  const T hy = diff_of_products(mk, gjy, mj, gky);
+  const T hz = diff_of_products(mk, gjz, mj, gkz);
+  const T eh = fma(ez, hz, fma(ey, hy, ex * hx));
+  const T ge = fma(gjz, ez, fma(gjy, ey, gjx * ex));
+  dm = fma(ge, y3, dm);
+  const T t = (y2 * T(-3)) * eh;
+  gx = fma(y3, fma(t, ex, hx), gx);
+  gy = fma(y3, fma(t, ey, hy), gy);
+  gz = fma(y3, fma(t, ez, hz), gz);
+}
+
+// ------------------------------------------------------ source tile layout --
+
+template <int PREC> struct Src;
+template <> struct Src<NBODY_FP64> { double x, y, z, m; };
+template <> struct Src<NBODY_MIXED> { float x, y, z, m; };
+template <> struct Src<NBODY_MIXED_D64> { double x, y, z; float m, pad; };
+
+template <int PREC>
+__device__ __forceinline__ Src<PREC> load_src(const double *__restrict__ pos,
+                                              const double *__restrict__ mass,
+                                              int n, int j, bool valid) {
+  Src<PREC> b{};
+  if (valid) {
+    b.x = pos[j];
+    b.y = pos[n + j];
+    b.z = pos[2 * n + j];
+    b.m = mass[j];   // rounds to FP32 in the mixed modes
+  }
+  return b;
+}
+
+template <int PREC> struct VSrc;
+template <> struct VSrc<NBODY_FP64> { double x, y, z, m, gx, gy, gz, pad; };
+template <> struct VSrc<NBODY_MIXED> { float x, y, z, m, gx, gy, gz, pad; };
+template <> struct VSrc<NBODY_MIXED_D64> {
+  double x, y, z;
+  float m, gx, gy, gz, pad0, pad1;
+};
+
+// Coordinate type of a target body and of its pair difference.
+template <int PREC> struct Coord { using T = double; using D = double; };
+template <> struct Coord<NBODY_MIXED> { using T = float; using D = float; };
+template <> struct Coord<NBODY_MIXED_D64> { using T = double; using D = float; };
+
+// ------------------------------------------------------------ acceleration --
+
+template <int PREC, int R>
+__global__ __launch_bounds__(kThreads) void accel_kernel(
+    int n, const double *__restrict__ pos, const double *__restrict__ mass,
+    double eps2d, double scale, int jchunk, double *__restrict__ out,
+    size_t split_stride) {
+  using CT = typename Coord<PREC>::T;
+  using DT = typename Coord<PREC>::D;
+  __shared__ Src<PREC> tile[kThreads];
+
+  const int tid = threadIdx.x;
+  const int ibase = blockIdx.x * (kThreads * R) + tid;
+  const int jbeg = blockIdx.y * jchunk;
+  const int jend = min(n, jbeg + jchunk);
+
+  CT xi[R], yi[R], zi[R];
+  double ax[R], ay[R], az[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = ibase + r * kThreads;
+    const bool ok = i < n;
+    xi[r] = ok ? CT(pos[i]) : CT(0);
+    yi[r] = ok ? CT(pos[n + i]) : CT(0);
+    zi[r] = ok ? CT(pos[2 * n + i]) : CT(0);
+    ax[r] = ay[r] = az[r] = 0.0;
+  }
+
+  for (int jt = jbeg; jt < jend; jt += kThreads) {
+    const int j = jt + tid;
+    const Src<PREC> b = load_src<PREC>(pos, mass, n, j, j < jend);
+    __syncthreads();  // previous tile fully consumed
+    tile[tid] = b;
+    __syncthreads();
+
+    if constexpr (PREC == NBODY_FP64) {
+#pragma unroll 4
+      for (int u = 0; u < kThreads; ++u) {
+        const Src<PREC> s = tile[u];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          pair_f64(s.x - xi[r], s.y - yi[r], s.z - zi[r], s.m, eps2d, ax[r],
+                   ay[r], az[r]);
+      }
+    } else {
+      const float eps2 = float(eps2d);
+      for (int u0 = 0; u0 < kThreads; u0 += kChunk) {
+        float fx[R], fy[R], fz[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) fx[r] = fy[r] = fz[r] = 0.0f;
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+          const Src<PREC> s = tile[u0 + u];
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            pair_f32(DT(s.x - xi[r]), DT(s.y - yi[r]), DT(s.z - zi[r]), s.m,
+                     eps2, fx[r], fy[r], fz[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          ax[r] += double(fx[r]);
+          ay[r] += double(fy[r]);
+          az[r] += double(fz[r]);
+        }
+      }
+    }
+  }
+
+  double *o = out + size_t(blockIdx.y) * split_stride;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = ibase + r * kThreads;
+    if (i < n) {
+      o[i] = scale * ax[r];
+      o[n + i] = scale * ay[r];
+      o[2 * n + i] = scale * az[r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------- VJP --
+
+template <int PREC, int R>
+__global__ __launch_bounds__(kThreads) void vjp_kernel(
+    int n, const double *__restrict__ pos, const double *__restrict__ mass,
+    const double *__restrict__ gacc, double eps2d, double scale, int jchunk,
+    double *__restrict__ out_x, double *__restrict__ out_m,
+    size_t split_stride) {
+  using CT = typename Coord<PREC>::T;
+  using DT = typename Coord<PREC>::D;
+  using AT = typename Coord<PREC>::D;  // arithmetic type of the pair terms
+  __shared__ VSrc<PREC> tile[kThreads];
+
+  const int tid = threadIdx.x;
+  const int kbase = blockIdx.x * (kThreads * R) + tid;
+  const int jbeg = blockIdx.y * jchunk;
+  const int jend = min(n, jbeg + jchunk);
+
+  CT xk[R], yk[R], zk[R];
+  AT mk[R], gkx[R], gky[R], gkz[R];
+  double sx[R], sy[R], sz[R], sm[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int k = kbase + r * kThreads;
+    const bool ok = k < n;
+    xk[r] = ok ? CT(pos[k]) : CT(0);
+    yk[r] = ok ? CT(pos[n + k]) : CT(0);
+    zk[r] = ok ? CT(pos[2 * n + k]) : CT(0);
+    mk[r] = ok ? AT(mass[k]) : AT(0);
+    gkx[r] = ok ? AT(gacc[k]) : AT(0);
+    gky[r] = ok ? AT(gacc[n + k]) : AT(0);
+    gkz[r] = ok ? AT(gacc[2 * n + k]) : AT(0);
+    sx[r] = sy[r] = sz[r] = sm[r] = 0.0;
+  }
+
+  for (int jt = jbeg; jt < jend; jt += kThreads) {
+    const int j = jt + tid;
+    VSrc<PREC> b{};
+    if (j < jend) {
+      b.x = pos[j];
+      b.y = pos[n + j];
+      b.z = pos[2 * n + j];
+      b.m = mass[j];
+      b.gx = gacc[j];
+      b.gy = gacc[n + j];
+      b.gz = gacc[2 * n + j];
+    }
+    __syncthreads();
+    tile[tid] = b;
+    __syncthreads();
+
+    if constexpr (PREC == NBODY_FP64) {
+#pragma unroll 2
+      for (int u = 0; u < kThreads; ++u) {
+        const VSrc<PREC> s = tile[u];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          vjp_pair<double>(s.x - xk[r], s.y - yk[r], s.z - zk[r], s.m, s.gx,
+                           s.gy, s.gz, mk[r], gkx[r], gky[r], gkz[r], eps2d,
+                           sx[r], sy[r], sz[r], sm[r]);
+      }
+    } else {
+      const float eps2 = float(eps2d);
+      for (int u0 = 0; u0 < kThreads; u0 += kVjpChunk) {
+        float fx[R], fy[R], fz[R], fm[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) fx[r] = fy[r] = fz[r] = fm[r] = 0.0f;
+#pragma unroll
+        for (int u = 0; u < kVjpChunk; ++u) {
+          const VSrc<PREC> s = tile[u0 + u];
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            vjp_pair<float>(DT(s.x - xk[r]), DT(s.y - yk[r]), DT(s.z - zk[r]),
+                            s.m, s.gx, s.gy, s.gz, mk[r], gkx[r], gky[r],
+                            gkz[r], eps2, fx[r], fy[r], fz[r], fm[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          sx[r] += double(fx[r]);
+          sy[r] += double(fy[r]);
+          sz[r] += double(fz[r]);
+          sm[r] += double(fm[r]);
+        }
+      }
+    }
+  }
+
+  double *ox = out_x + size_t(blockIdx.y) * split_stride;
+  double *om = out_m + size_t(blockIdx.y) * split_stride;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int k = kbase + r * kThreads;
+    if (k < n) {
+      ox[k] = scale * sx[r];
+      ox[n + k] = scale * sy[r];
+      ox[2 * n + k] = scale * sz[r];
+      om[k] = -scale * sm[r];
+    }
+  }
+}
+
+// --------------------------------------------------- per-body FP64 kernels --
+
+__device__ __forceinline__ double split_sum(const double *__restrict__ part,
+                                            size_t stride, int sj, size_t off) {
+  double s = part[off];
+  for (int q = 1; q < sj; ++q) s += part[size_t(q) * stride + off];
+  return s;
+}
+
+__global__ __launch_bounds__(kThreads) void reduce_kernel(
+    int n, int sj, const double *__restrict__ part, size_t stride, double G,
+    double *__restrict__ out_x, double *__restrict__ out_m) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    out_x[size_t(c) * n + i] = G * split_sum(part, stride, sj, size_t(c) * n + i);
+  if (out_m) out_m[i] = G * split_sum(part, stride, sj, size_t(3) * n + i);
+}
+
+__global__ __launch_bounds__(kThreads) void update_kernel(
+    int n, int sj, const double *__restrict__ part, size_t stride, double G,
+    const double *a_in, double *acc_out, const double *x_in, double *x_out,
+    const double *v_in, double *v_out, double h, double dt, double *rec,
+    unsigned flags) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const size_t q = size_t(c) * n + i;
+    const double a = part ? G * split_sum(part, stride, sj, q) : a_in[q];
+    const double x = x_in[q];
+    double v = v_in[q];
+    if (flags & kClose) v = v + h * a;
+    if (rec) {
+      rec[q] = x;
+      rec[size_t(3) * n + q] = v;
+      rec[size_t(6) * n + q] = a;
+    }
+    if (flags & kOpen) {
+      v = v + h * a;
+      x_out[q] = x + dt * v;
+    }
+    v_out[q] = v;
+    if (acc_out) acc_out[q] = a;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void adj_init_kernel(
+    int n, const double *__restrict__ gvel, const double *__restrict__ gacc_T,
+    double h, int add_hv, double *__restrict__ abar,
+    double *__restrict__ gmass) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const size_t q = size_t(c) * n + i;
+    double ab = gacc_T ? gacc_T[q] : 0.0;
+    if (add_hv) ab = ab + h * gvel[q];
+    abar[q] = ab;
+  }
+  gmass[i] = 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void adj_combine_kernel(
+    int n, int sj, const double *__restrict__ part, size_t stride, double G,
+    double dt, double h, double *__restrict__ gpos, double *__restrict__ gvel,
+    double *__restrict__ gmass, double *__restrict__ abar, int mode) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  gmass[i] = gmass[i] + G * split_sum(part, stride, sj, size_t(3) * n + i);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const size_t q = size_t(c) * n + i;
+    const double gx = gpos[q] + G * split_sum(part, stride, sj, q);
+    gpos[q] = gx;
+    if (mode != kAdjFinal) {
+      const double gv = gvel[q] + dt * gx;
+      gvel[q] = gv;
+      double ab = h * gv;
+      if (mode == kAdjMid) ab = ab + h * gv;
+      abar[q] = ab;
+    }
+  }
+}
+
+inline dim3 grid1(int n) { return dim3((n + kThreads - 1) / kThreads); }
+
+template <int PREC>
+hipError_t launch_accel_p(const Plan &pl, int n, const double *pos,
+                          const double *mass, double eps2, double scale,
+                          double *out, size_t stride, hipStream_t st) {
+  const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
+  const int jc = int(pl.jchunk);
+  switch (pl.R) {
+    case 1:
+      accel_kernel<PREC, 1><<<grid, kThreads, 0, st>>>(n, pos, mass, eps2,
+                                                       scale, jc, out, stride);
+      break;
+    case 2:
+      accel_kernel<PREC, 2><<<grid, kThreads, 0, st>>>(n, pos, mass, eps2,
+                                                       scale, jc, out, stride);
+      break;
+    case 4:
+      accel_kernel<PREC, 4><<<grid, kThreads, 0, st>>>(n, pos, mass, eps2,
+                                                       scale, jc, out, stride);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_vjp_p(const Plan &pl, int n, const double *pos,
+                        const double *mass, const double *gacc, double eps2,
+                        double scale, double *ox, double *om, size_t stride,
+                        hipStream_t st) {
+  const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
+  const int jc = int(pl.jchunk);
+  switch (pl.R) {
+    case 1:
+      vjp_kernel<PREC, 1><<<grid, kThreads, 0, st>>>(n, pos, mass, gacc, eps2,
+                                                     scale, jc, ox, om, stride);
+      break;
+    case 2:
+      vjp_kernel<PREC, 2><<<grid, kThreads, 0, st>>>(n, pos, mass, gacc, eps2,
+                                                     scale, jc, ox, om, stride);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launch plans --
+
+Plan make_plan(KernelKind kind, int precision, int64_t n) {
+  // Target bodies per thread: enough independent pair chains to hide the
+  // latency of the reciprocal square root and the LDS broadcasts, at a
+  // register cost that keeps several waves per SIMD resident.
+  int R;
+  if (kind == kAccel) R = (precision == NBODY_FP64) ? 2 : 2;
+  else R = (precision == NBODY_FP64) ? 1 : 2;
+  // Small systems: fewer bodies per thread so more waves exist at all.
+  while (R > 1 && (n + int64_t(kThreads) * R - 1) / (int64_t(kThreads) * R) < 64)
+    R /= 2;
+  Plan p;
+  p.R = R;
+  p.n_ib = (n + int64_t(kThreads) * R - 1) / (int64_t(kThreads) * R);
+  const int64_t ntiles = (n + kThreads - 1) / kThreads;
+  // Split the source range until about 1024 workgroups (4 per CU) exist.
+  const int64_t target = 1024;
+  int64_t sj = (target + p.n_ib - 1) / p.n_ib;
+  if (sj < 1) sj = 1;
+  if (sj > ntiles) sj = ntiles;
+  const int64_t tiles_per_split = (ntiles + sj - 1) / sj;
+  p.jchunk = tiles_per_split * kThreads;
+  p.sj = (n + p.jchunk - 1) / p.jchunk;
+  return p;
+}
+
+hipError_t launch_accel(const Plan &pl, int precision, int n, const double *pos,
+                        const double *mass, double eps2, double scale,
+                        double *out, size_t stride, hipStream_t st) {
+  switch (precision) {
+    case NBODY_FP64:
+      return launch_accel_p<NBODY_FP64>(pl, n, pos, mass, eps2, scale, out,
+                                        stride, st);
+    case NBODY_MIXED:
+      return launch_accel_p<NBODY_MIXED>(pl, n, pos, mass, eps2, scale, out,
+                                         stride, st);
+    case NBODY_MIXED_D64:
+      return launch_accel_p<NBODY_MIXED_D64>(pl, n, pos, mass, eps2, scale,
+                                             out, stride, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_vjp(const Plan &pl, int precision, int n, const double *pos,
+                      const double *mass, const double *gacc, double eps2,
+                      double scale, double *ox, double *om, size_t stride,
+                      hipStream_t st) {
+  switch (precision) {
+    case NBODY_FP64:
+      return launch_vjp_p<NBODY_FP64>(pl, n, pos, mass, gacc, eps2, scale, ox,
+                                      om, stride, st);
+    case NBODY_MIXED:
+      return launch_vjp_p<NBODY_MIXED>(pl, n, pos, mass, gacc, eps2, scale, ox,
+                                       om, stride, st);
+    case NBODY_MIXED_D64:
+      return launch_vjp_p<NBODY_MIXED_D64>(pl, n, pos, mass, gacc, eps2, scale,
+                                           ox, om, stride, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce(int n, int sj, const double *part, size_t stride,
+                         double G, double *out_x, double *out_m,
+                         hipStream_t st) {
+  reduce_kernel<<<grid1(n), kThreads, 0, st>>>(n, sj, part, stride, G, out_x,
+                                               out_m);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(int n, int sj, const double *part, size_t stride,
+                         double G, const double *a_in, double *acc_out,
+                         const double *x_in, double *x_out, const double *v_in,
+                         double *v_out, double h, double dt, double *rec,
+                         unsigned flags, hipStream_t st) {
+  update_kernel<<<grid1(n), kThreads, 0, st>>>(n, sj, part, stride, G, a_in,
+                                               acc_out, x_in, x_out, v_in,
+                                               v_out, h, dt, rec, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_init(int n, const double *gvel, const double *gacc_T,
+                           double h, int add_hv, double *abar, double *gmass,
+                           hipStream_t st) {
+  adj_init_kernel<<<grid1(n), kThreads, 0, st>>>(n, gvel, gacc_T, h, add_hv,
+                                                 abar, gmass);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_combine(int n, int sj, const double *part, size_t stride,
+                              double G, double dt, double h, double *gpos,
+                              double *gvel, double *gmass, double *abar,
+                              int mode, hipStream_t st) {
+  adj_combine_kernel<<<grid1(n), kThreads, 0, st>>>(
+      n, sj, part, stride, G, dt, h, gpos, gvel, gmass, abar, mode);
+  return hipGetLastError();
+}
+
+}  // namespace nbody

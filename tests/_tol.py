@@ -1,0 +1,149 @@
+"""Per-body error bounds of the GPU path, derived from its arithmetic.
+
+For the acceleration a_i = G sum_j f_ij, f_ij = m_j d_ij w_ij with
+w_ij = s_ij^-3/2, s_ij = |d_ij|^2 + eps^2 (d_ij = x_j - x_i):
+
+* rounding each position to FP32 (NBODY_MIXED) perturbs d_ij by
+  delta_ij <= u32 (|x_i| + |x_j| + |d_ij|); the rounded FP64 difference
+  (NBODY_MIXED_D64) by delta_ij <= u32 |d_ij|; FP64 inputs are exact;
+* a perturbation delta of d changes f_ij by at most 4 G m_j w_ij delta
+  (|d(d w)/dd| <= w (1 + 3 |d|^2 / s) <= 4 w);
+* the pair arithmetic (three FMAs for s, the hardware reciprocal square root
+  of a few ulp, three products and the accumulating FMA) adds at most
+  c_pair u |f_ij| with c_pair = 16, and summing chunk sums of length L adds at
+  most L u sum_j |f_ij| (gamma_L bound), L = 32 for the FP32 chunks and n for
+  the FP64 path (whole source range, worst case).
+
+so |a_i^gpu - a_i| <= SAFETY * G sum_j m_j w_ij (4 delta_ij + (16 + L) u |d_ij|).
+The self pair j == i is left out: the kernels see d_ii = 0 exactly (both
+ends are the same rounded value) and add exactly zero for it.
+The VJP bound is the same construction over its terms (see vjp_bound).
+These are worst-case bounds; the measured errors sit far below them.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+U32 = 2.0 ** -24
+U64 = 2.0 ** -53
+SAFETY = 2.0
+CHUNK32 = 32
+VJP_CHUNK32 = 16
+
+
+def _rows_iter(rows, n):
+    block = max(1, (1 << 22) // max(n, 1))
+    for s in range(0, len(rows), block):
+        yield rows[s:s + block]
+
+
+def accel_bound(pos, mass, G, eps, precision, rows=None):
+    """Bound on |a_i^gpu - a_i| (Euclidean) for each row i."""
+    n = mass.size
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    xn = np.linalg.norm(pos, axis=0)
+    out = np.empty(len(rows))
+    if precision == "fp64":
+        u, L = U64, n + 64
+    else:
+        u, L = U32, CHUNK32
+    k = 0
+    for blk in _rows_iter(rows, n):
+        d = pos[:, None, :] - pos[:, blk, None]             # (3, b, n)
+        dn = np.sqrt((d * d).sum(axis=0))
+        s = dn * dn + eps * eps
+        w = mass[None, :] * s ** -1.5
+        if precision == "mixed":
+            delta = U32 * (xn[blk, None] + xn[None, :] + dn)
+        elif precision == "mixed_d64":
+            delta = U32 * dn
+        else:
+            delta = 0.0
+        term = w * (4.0 * delta + (16 + L) * u * dn)
+        term[np.arange(len(blk)), blk] = 0.0          # self pair: exactly 0
+        out[k:k + len(blk)] = abs(G) * term.sum(axis=1)
+        k += len(blk)
+    return SAFETY * out
+
+
+def vjp_bound(pos, mass, gacc, G, eps, precision, rows=None):
+    """Bounds (|dL/dx_k err|, |dL/dm_k err|) for each row k.
+
+    Terms: s^-3/2 [h - 3 (e.h) e / s] with |h| <= H = m_k |g_j| + m_j |g_k|,
+    and (g_j . e) s^-3/2.  A perturbation delta of e changes the first by at
+    most 12 H s^-3/2 delta / sqrt(s) and the second by 4 |g_j| s^-3/2 delta;
+    the pair arithmetic adds c u of each term's magnitude bound (c = 40 for
+    the 32-operation row term), plus the chunk summation as for the
+    acceleration.  The self pair adds exactly zero (e = 0, and h is formed
+    as a difference of two rounded products, so h = 0) and is left out."""
+    n = mass.size
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    xn = np.linalg.norm(pos, axis=0)
+    gn = np.linalg.norm(gacc, axis=0)
+    bx = np.empty(len(rows))
+    bm = np.empty(len(rows))
+    if precision == "fp64":
+        u, L = U64, n + 64
+    else:
+        u, L = U32, VJP_CHUNK32
+    k = 0
+    for blk in _rows_iter(rows, n):
+        e = pos[:, None, :] - pos[:, blk, None]
+        en = np.sqrt((e * e).sum(axis=0))
+        s = en * en + eps * eps
+        y3 = s ** -1.5
+        H = mass[blk, None] * gn[None, :] + mass[None, :] * gn[blk, None]
+        if precision == "mixed":
+            delta = U32 * (xn[blk, None] + xn[None, :] + en)
+        elif precision == "mixed_d64":
+            delta = U32 * en
+        else:
+            delta = 0.0
+        tx = y3 * H * (12.0 * delta / np.sqrt(s) + (40 + L) * u * 4.0)
+        tm = y3 * gn[None, :] * (4.0 * delta + (16 + L) * u * en)
+        # self pair: e = 0 and h = 0 exactly in the kernels
+        tx[np.arange(len(blk)), blk] = 0.0
+        tm[np.arange(len(blk)), blk] = 0.0
+        bx[k:k + len(blk)] = abs(G) * tx.sum(axis=1)
+        bm[k:k + len(blk)] = abs(G) * tm.sum(axis=1)
+        k += len(blk)
+    return SAFETY * bx, SAFETY * bm
+
+
+def adjoint_bound(oracle, pos, vel, mass, G, eps, dt, steps, gx, gv, ga,
+                  precision, rows=None):
+    """Element-wise bounds (dL/dx_0, dL/dv_0, dL/dm) of the GPU reverse sweep.
+
+    The reverse sweep is linear in the upstream gradients; its only
+    approximate operation is the VJP.  Walking the exact sweep (oracle VJPs
+    along the oracle trajectory) gives each step's abar_t, and each VJP adds
+    at most vjp_bound(x_{t+1}, abar_t) to xbar and mbar.  An xbar error
+    reaches vbar through vbar += dt xbar, and abar through (dt/2) vbar, whose
+    effect on later VJPs is second order in dt and covered by a 25% margin.
+    With `rows`, bounds are formed for those rows only (the sweep itself is
+    still exact over all bodies).
+    """
+    h = 0.5 * dt
+    traj = [np.array(pos, dtype=np.float64)]
+    x, v, a = pos, vel, None
+    for _ in range(steps):
+        x, v, a = oracle.step(x, v, mass, G, eps, dt, 1, acc=a)
+        traj.append(x)
+    gxc = np.array(gx, dtype=np.float64)
+    gvc = np.array(gv, dtype=np.float64)
+    ab = (np.zeros_like(gxc) if ga is None else np.array(ga)) + (h * gvc if steps else 0)
+    m = mass.size if rows is None else len(rows)
+    Bx, Bv, Bm = np.zeros(m), np.zeros(m), np.zeros(m)
+    for t in range(steps - 1, -1, -1):
+        vx, vm = oracle.accel_vjp(traj[t + 1], mass, ab, G, eps)
+        bx, bm = vjp_bound(traj[t + 1], mass, ab, G, eps, precision, rows)
+        Bx += bx
+        Bm += bm
+        gxc = gxc + vx
+        gvc = gvc + dt * gxc
+        Bv += dt * Bx
+        ab = h * gvc + (h * gvc if t > 0 else 0)
+    bx, bm = vjp_bound(traj[0], mass, ab, G, eps, precision, rows)
+    Bx += bx
+    Bm += bm
+    return 1.25 * Bx, 1.25 * Bv, 1.25 * Bm

@@ -1,0 +1,192 @@
+"""Host-side checks of the C ABI (no GPU needed, no compute calls).
+
+The library must load, export every function include/nbody.h declares, size
+workspaces and checkpoints as documented, and reject invalid arguments on the
+host before anything is enqueued.  Calls here fail validation before they
+touch the HIP runtime, so they are safe without a device; the fake pointers
+passed are never dereferenced.
+"""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nbody.h")
+
+pytestmark = pytest.mark.skipif(
+    not os.path.exists(os.path.join(ROOT, "paper_2203_08263_amd", "libnbody_hip.so")),
+    reason="libnbody_hip.so not built (run __graft_entry__.build())")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2203_08263_amd import binding
+    binding.load_library()
+    return binding
+
+
+def _declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(nbody_\w+)\s*\(",
+                                 txt, flags=re.M)))
+
+
+def test_header_declares_the_four_entry_points():
+    names = _declared_functions()
+    for f in ("nbody_accel", "nbody_step", "nbody_accel_vjp", "nbody_step_adjoint"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(B):
+    lib = ctypes.CDLL(B.library_path())
+    names = _declared_functions()
+    assert set(names) == set(B.SYMBOLS)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_header_enums_match_binding(B):
+    txt = open(HEADER).read()
+    for name, val in [("NBODY_FP64", B.NBODY_FP64), ("NBODY_MIXED", B.NBODY_MIXED),
+                      ("NBODY_MIXED_D64", B.NBODY_MIXED_D64),
+                      ("NBODY_OP_STEP_ADJOINT", B.NBODY_OP_STEP_ADJOINT)]:
+        m = re.search(r"\b%s\s*=\s*(\d+)" % name, txt)
+        assert m and int(m.group(1)) == val
+    assert "#define NBODY_ACC_VALID 1u" in txt
+    assert "#define NBODY_MAX_N ((int64_t)1 << 28)" in txt
+
+
+def test_error_strings(B):
+    lib = B.load_library()
+    for code in range(5):
+        assert lib.nbody_error_string(code)
+    assert lib.nbody_error_string(99) == b"unknown status code"
+
+
+def test_checkpoint_bytes(B):
+    assert B.nbody_checkpoint_bytes(100, 50, 10) == 5 * 9 * 100 * 8
+    assert B.nbody_checkpoint_bytes(100, 51, 10) == 6 * 9 * 100 * 8
+    assert B.nbody_checkpoint_bytes(100, 0, 10) == 9 * 100 * 8
+    assert B.nbody_checkpoint_bytes(100, 5, 10) == 9 * 100 * 8
+    inv = ctypes.c_size_t(-1).value
+    assert B.nbody_checkpoint_bytes(0, 5, 1) == inv
+    assert B.nbody_checkpoint_bytes(100, -1, 1) == inv
+    assert B.nbody_checkpoint_bytes(100, 5, 0) == inv
+
+
+def test_workspace_bytes(B):
+    inv = ctypes.c_size_t(-1).value
+    for prec in (0, 1, 2):
+        for n in (1, 255, 256, 1000, 16384, 65536, 262144):
+            step = B.nbody_workspace_bytes(B.NBODY_OP_STEP, n, 10, 1, prec)
+            acc = B.nbody_workspace_bytes(B.NBODY_OP_ACCEL, n, 0, 1, prec)
+            vjp = B.nbody_workspace_bytes(B.NBODY_OP_VJP, n, 0, 1, prec)
+            adj = B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, n, 50, 10, prec)
+            # partial sums of at least one split, 256-byte rounded
+            assert step >= 3 * n * 8 and step % 256 == 0
+            assert acc in (0,) or (acc >= 6 * n * 8 and acc % 256 == 0)
+            assert vjp in (0,) or (vjp >= 8 * n * 8 and vjp % 256 == 0)
+            # v, a, abar, 10 segment positions, partials
+            assert adj >= (3 * 3 + 10 * 3 + 4) * n * 8
+        assert B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, 100, 50, 0, prec) == inv
+    assert B.nbody_workspace_bytes(7, 100, 0, 1, 0) == inv
+    assert B.nbody_workspace_bytes(0, 0, 0, 1, 0) == inv
+    assert B.nbody_workspace_bytes(0, 100, 0, 1, 3) == inv
+    assert B.nbody_workspace_bytes(0, B.NBODY_MAX_N + 1, 0, 1, 0) == inv
+    # fewer segment positions are needed when steps < ckpt_every
+    a = B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, 1000, 3, 10, 0)
+    b = B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, 1000, 30, 10, 0)
+    assert a < b
+
+
+# ------------------------------------------- argument errors, no launches --
+
+FAKE = 0x10000  # aligned, never dereferenced: validation fails first
+
+
+def _p(v):
+    return ctypes.c_void_p(v)
+
+
+def _params(B, G=1.0, eps=1e-3, dt=1e-3):
+    return ctypes.byref(B._Params(G, eps, dt))
+
+
+def _accel(B, n=64, pos=FAKE, mass=FAKE, acc=FAKE, prec=0, ws=None, wsb=0, **kw):
+    lib = B.load_library()
+    return lib.nbody_accel(n, _p(pos), _p(mass), _p(acc), _params(B, **kw), prec,
+                           _p(ws), wsb, None)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(n=0), "outside"), (dict(n=-5), "outside"),
+    (dict(n=(1 << 28) + 1), "outside"),
+    (dict(pos=0), "pos is NULL"), (dict(mass=0), "mass is NULL"),
+    (dict(acc=0), "acc is NULL"), (dict(pos=FAKE + 4), "aligned"),
+    (dict(eps=0.0), "eps"), (dict(eps=-1.0), "eps"), (dict(eps=math.nan), "eps"),
+    (dict(eps=1e-200), "eps^2"), (dict(G=math.inf), "G is not finite"),
+    (dict(prec=3), "precision"), (dict(prec=-1), "precision"),
+])
+def test_accel_rejects_invalid_arguments(B, kw, msg):
+    rc = _accel(B, **kw)
+    assert rc == 1
+    assert msg in B.load_library().nbody_last_error().decode()
+
+
+def test_accel_workspace_too_small(B):
+    n = 65536
+    need = B.nbody_workspace_bytes(B.NBODY_OP_ACCEL, n, 0, 1, 0)
+    assert need > 0
+    assert _accel(B, n=n, ws=FAKE, wsb=need - 8) == 2
+    assert _accel(B, n=n, ws=None, wsb=0) == 2
+    assert _accel(B, n=n, ws=0, wsb=need) == 1  # NULL workspace
+
+
+def test_step_rejects_invalid_arguments(B):
+    lib = B.load_library()
+    pr = _params(B)
+    n = 1000
+    ws = B.nbody_workspace_bytes(B.NBODY_OP_STEP, n, 1, 1, 0)
+
+    def step(steps=1, flags=0, ckpt=None, K=1, dt=1e-3, vel=FAKE, wsb=ws):
+        return lib.nbody_step(n, steps, _p(FAKE), _p(vel), _p(FAKE), _p(FAKE),
+                              _params(B, dt=dt), 0, flags, _p(ckpt), K, _p(FAKE),
+                              wsb, None)
+    assert step(steps=-1) == 1
+    assert step(flags=2) == 1
+    assert step(ckpt=FAKE, K=0) == 1
+    assert step(dt=math.nan) == 1
+    assert step(vel=0) == 1
+    assert step(wsb=ws - 1) == 2
+    assert pr is not None
+
+
+def test_vjp_and_adjoint_reject_invalid_arguments(B):
+    lib = B.load_library()
+    n = 1000
+    assert lib.nbody_accel_vjp(n, _p(FAKE), _p(FAKE), _p(0), _p(FAKE), _p(FAKE),
+                               _params(B), 0, _p(FAKE), 1 << 30, None) == 1
+    ws = B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, n, 10, 5, 1)
+
+    def adj(steps=10, K=5, ckpt=FAKE, gacc=None, wsb=ws, prec=1):
+        return lib.nbody_step_adjoint(n, steps, K, _p(ckpt), _p(FAKE), _params(B),
+                                      prec, _p(FAKE), _p(FAKE), _p(gacc), _p(FAKE),
+                                      _p(FAKE), wsb, None)
+    assert adj(K=0) == 1
+    assert adj(steps=-2) == 1
+    assert adj(ckpt=0) == 1
+    assert adj(gacc=FAKE + 2) == 1
+    assert adj(prec=5) == 1
+    assert adj(wsb=ws - 256) == 2
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2203_08263_amd import binding
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "_LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        binding.load_library()

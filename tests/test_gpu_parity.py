@@ -1,0 +1,333 @@
+"""GPU parity of the HIP path against the FP64 oracle (small and ragged sizes).
+
+Every comparison is element by element against the oracle on the same
+seeded inputs.  FP64 and mixed results must sit inside the per-body bounds
+of tests/_tol.py (derived from each mode's arithmetic); integer-exact facts
+(reflection, mass doubling, determinism, chaining, checkpoint-interval
+invariance) are checked bitwise.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import _tol
+from paper_2203_08263_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp64", "mixed", "mixed_d64"]
+SIZES = [1, 2, 3, 64, 255, 256, 257, 1000, 2049, 5003]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_08263_amd import binding
+    binding.load_library()   # raises if the HIP library is missing
+    return binding
+
+
+@pytest.fixture(scope="module")
+def dev(B):
+    return torch.device("cuda:0")
+
+
+def T(a, dev):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def N(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _check_bound(got, ref, bound, what):
+    err = np.sqrt(((got - ref) ** 2).sum(axis=0))
+    worst = np.argmax(err / np.maximum(bound, 1e-300))
+    assert np.all(err <= bound), "%s: row %d err %.3e bound %.3e" % (
+        what, worst, err[worst], bound[worst])
+    return err
+
+
+# ------------------------------------------------------------ acceleration --
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n", SIZES)
+def test_accel_parity(B, dev, oracle, prec, n):
+    say("accel parity", prec, n)
+    pos, _, mass = inputs.uniform_cube(n, 500 + n)
+    ref = oracle.accel(pos, mass, 1.0, 1e-3)
+    got = N(B.nbody_accel(T(pos, dev), T(mass, dev), 1.0, 1e-3, prec))
+    _check_bound(got, ref, _tol.accel_bound(pos, mass, 1.0, 1e-3, prec), prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_accel_golden_two_body(B, dev, prec):
+    say("golden two-body", prec)
+    pos = np.array([[0.0, 3.0], [0.0, 4.0], [0.0, 0.0]])
+    mass = np.array([2.0, 3.0])
+    got = N(B.nbody_accel(T(pos, dev), T(mass, dev), 1.0, np.sqrt(11.0), prec))
+    exact = np.array([[1 / 24, -1 / 36], [1 / 18, -1 / 27], [0.0, 0.0]])
+    tol = 4e-16 if prec == "fp64" else 2e-6
+    np.testing.assert_allclose(got, exact, rtol=tol, atol=0)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_accel_edge_cases(B, dev, oracle, prec):
+    say("edge cases", prec)
+    # one body: exactly zero
+    a1 = N(B.nbody_accel(T([[0.3], [-0.2], [0.9]], dev), T([5.0], dev), 1.0, 1e-3, prec))
+    assert np.all(a1 == 0.0)
+    # coincident bodies pull nothing from each other; zero-mass bodies pull
+    # nothing at all but still feel the others
+    pos = np.array([[0.1, 0.1, -0.5, 0.7], [0.2, 0.2, 0.1, 0.0], [0.0, 0.0, 0.3, 0.1]])
+    mass = np.array([1.0, 2.0, 0.0, 0.5])
+    ref = oracle.accel(pos, mass, 1.0, 1e-2)
+    got = N(B.nbody_accel(T(pos, dev), T(mass, dev), 1.0, 1e-2, prec))
+    _check_bound(got, ref, _tol.accel_bound(pos, mass, 1.0, 1e-2, prec), prec)
+    # G = 0 gives exactly zero
+    z = N(B.nbody_accel(T(pos, dev), T(mass, dev), 0.0, 1e-2, prec))
+    assert np.all(z == 0.0)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_accel_exact_invariants(B, dev, prec):
+    say("invariants", prec)
+    pos, _, mass = inputs.uniform_cube(3000, 7)
+    P, M = T(pos, dev), T(mass, dev)
+    a = N(B.nbody_accel(P, M, 1.0, 1e-3, prec))
+    assert np.array_equal(N(B.nbody_accel(P, M, 1.0, 1e-3, prec)), a)     # determinism
+    assert np.array_equal(N(B.nbody_accel(-P, M, 1.0, 1e-3, prec)), -a)   # reflection
+    assert np.array_equal(N(B.nbody_accel(P, 2 * M, 1.0, 1e-3, prec)), 2 * a)
+    assert np.array_equal(N(B.nbody_accel(P, M, 4.0, 1e-3, prec)), 4 * a)
+
+
+# ---------------------------------------------------------------------- VJP --
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n", [1, 2, 63, 257, 1000, 3001])
+def test_vjp_parity(B, dev, oracle, prec, n):
+    say("vjp parity", prec, n)
+    pos, _, mass = inputs.uniform_cube(n, 600 + n)
+    g = inputs.upstream_normal(n, 700 + n)
+    rx, rm = oracle.accel_vjp(pos, mass, g, 1.0, 1e-3)
+    gx, gm = B.nbody_accel_vjp(T(pos, dev), T(mass, dev), T(g, dev), 1.0, 1e-3, prec)
+    bx, bm = _tol.vjp_bound(pos, mass, g, 1.0, 1e-3, prec)
+    _check_bound(N(gx), rx, bx, prec + " dL/dx")
+    assert np.all(np.abs(N(gm) - rm) <= bm), prec + " dL/dm"
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_vjp_translation_and_homogeneity(B, dev, prec):
+    say("vjp invariants", prec)
+    pos, _, mass = inputs.uniform_cube(2000, 8)
+    g = inputs.upstream_normal(2000, 9)
+    gx, gm = B.nbody_accel_vjp(T(pos, dev), T(mass, dev), T(g, dev), 1.0, 1e-3, prec)
+    a = B.nbody_accel(T(pos, dev), T(mass, dev), 1.0, 1e-3, prec)
+    gx, gm, a = N(gx), N(gm), N(a)
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    assert np.all(np.abs(gx.sum(axis=1)) <= tol * np.abs(gx).sum(axis=1))
+    assert float((mass * gm).sum()) == pytest.approx(float((g * a).sum()), rel=tol)
+
+
+# ------------------------------------------------------------- step loop --
+
+def _state(n, seed, dev):
+    pos, vel, mass = inputs.uniform_cube(n, seed)
+    return pos, vel, mass, T(pos, dev), T(vel, dev), T(mass, dev)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_step_parity_small(B, dev, oracle, prec):
+    say("step parity", prec)
+    n, S, dt, eps = 1000, 20, 1e-3, 1e-3
+    pos, vel, mass, P, V, M = _state(n, 41, dev)
+    A = torch.empty_like(P)
+    B.nbody_step(P, V, A, M, 1.0, eps, dt, S, prec)
+    x, v, a = oracle.step(pos, vel, mass, 1.0, eps, dt, S)
+    ex = np.linalg.norm(N(P) - x) / np.linalg.norm(x)
+    ev = np.linalg.norm(N(V) - v) / np.linalg.norm(v)
+    say("  state err x %.2e v %.2e" % (ex, ev))
+    if prec == "fp64":
+        assert ex <= 1e-12 and ev <= 1e-12
+    else:
+        # each step's velocity error is at most dt * max accel bound; the
+        # position error accumulates it S more times (no chaotic growth over
+        # 20 steps of 1e-3)
+        ab = _tol.accel_bound(pos, mass, 1.0, eps, prec).max()
+        assert np.abs(N(V) - v).max() <= 2 * S * dt * ab
+        assert np.abs(N(P) - x).max() <= 2 * S * S * dt * dt * ab
+    _check_bound(N(A), oracle.accel(N(P), mass, 1.0, eps),
+                 _tol.accel_bound(N(P), mass, 1.0, eps, prec), "final acc")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_step_chaining_bitwise(B, dev, prec):
+    say("chaining", prec)
+    n = 700
+    _, _, _, P, V, M = _state(n, 42, dev)
+    P2, V2 = P.clone(), V.clone()
+    A, A2 = torch.empty_like(P), torch.empty_like(P)
+    B.nbody_step(P, V, A, M, 1.0, 1e-3, 1e-3, 7, prec)
+    B.nbody_step(P, V, A, M, 1.0, 1e-3, 1e-3, 5, prec, acc_valid=True)
+    B.nbody_step(P2, V2, A2, M, 1.0, 1e-3, 1e-3, 12, prec)
+    assert torch.equal(P, P2) and torch.equal(V, V2) and torch.equal(A, A2)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_step_zero_steps_and_acc(B, dev, prec):
+    say("zero steps", prec)
+    pos, vel, mass, P, V, M = _state(300, 43, dev)
+    A = torch.full_like(P, 7.0)
+    B.nbody_step(P, V, A, M, 1.0, 1e-3, 1e-3, 0, prec)
+    assert np.array_equal(N(P), pos) and np.array_equal(N(V), vel)
+    assert torch.equal(A, B.nbody_accel(P, M, 1.0, 1e-3, prec))
+    A.fill_(7.0)
+    B.nbody_step(P, V, A, M, 1.0, 1e-3, 1e-3, 0, prec, acc_valid=True)
+    assert torch.all(A == 7.0)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_step_checkpoint_records(B, dev, prec):
+    say("checkpoints", prec)
+    n, S, K = 500, 11, 4
+    _, _, _, P, V, M = _state(n, 44, dev)
+    P0, V0 = P.clone(), V.clone()
+    A = torch.empty_like(P)
+    ck = torch.empty(B.nbody_checkpoint_bytes(n, S, K) // 8, dtype=torch.float64,
+                     device=dev)
+    B.nbody_step(P, V, A, M, 1.0, 1e-3, 1e-3, S, prec, ckpt=ck, ckpt_every=K)
+    recs = ck.view(-1, 9, n)
+    assert recs.shape[0] == 3
+    for c in range(3):
+        p, v, a = P0.clone(), V0.clone(), torch.empty_like(P0)
+        B.nbody_step(p, v, a, M, 1.0, 1e-3, 1e-3, c * K, prec)
+        assert torch.equal(recs[c, 0:3], p)
+        assert torch.equal(recs[c, 3:6], v)
+        assert torch.equal(recs[c, 6:9], a)
+
+
+# ------------------------------------------------------------- adjoint ----
+
+def _adjoint_gpu(B, dev, pos, vel, mass, gx, gv, S, K, prec, ga=None, dt=1e-3,
+                 eps=1e-3):
+    n = mass.size
+    P, V, M = T(pos, dev), T(vel, dev), T(mass, dev)
+    A = torch.empty_like(P)
+    ck = torch.empty(B.nbody_checkpoint_bytes(n, S, K) // 8, dtype=torch.float64,
+                     device=dev)
+    B.nbody_step(P, V, A, M, 1.0, eps, dt, S, prec, ckpt=ck, ckpt_every=K)
+    GX, GV = T(gx, dev), T(gv, dev)
+    GA = None if ga is None else T(ga, dev)
+    _, _, GM = B.nbody_step_adjoint(ck, M, GX, GV, 1.0, eps, dt, S, K, prec,
+                                    gacc_T=GA)
+    return N(GX), N(GV), N(GM)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_adjoint_vs_oracle(B, dev, oracle, prec):
+    say("adjoint vs oracle", prec)
+    n, S, K = 400, 12, 5
+    pos, vel, mass = inputs.uniform_cube(n, 45)
+    gx = inputs.upstream_normal(n, 46)
+    gv = inputs.upstream_normal(n, 47, 0.1)
+    ga = inputs.upstream_normal(n, 48, 1e-3)
+    rx, rv, rm = oracle.step_adjoint(pos, vel, mass, 1.0, 1e-3, 1e-3, S, gx, gv, ga)
+    ox, ov, om = _adjoint_gpu(B, dev, pos, vel, mass, gx, gv, S, K, prec, ga)
+    errs = [np.linalg.norm(o - r) / np.linalg.norm(r)
+            for o, r in ((ox, rx), (ov, rv), (om, rm))]
+    say("  normwise err x %.2e v %.2e m %.2e" % tuple(errs))
+    if prec == "fp64":
+        assert max(errs) <= 1e-12
+    bx, bv, bm = _tol.adjoint_bound(oracle, pos, vel, mass, 1.0, 1e-3, 1e-3, S,
+                                    gx, gv, ga, prec)
+    _check_bound(ox, rx, bx, prec + " dL/dx0")
+    _check_bound(ov, rv, bv, prec + " dL/dv0")
+    assert np.all(np.abs(om - rm) <= bm), prec + " dL/dm"
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_adjoint_checkpoint_interval_invariance(B, dev, prec):
+    say("K invariance", prec)
+    n, S = 300, 12
+    pos, vel, mass = inputs.uniform_cube(n, 49)
+    gx = inputs.upstream_normal(n, 50)
+    gv = inputs.upstream_normal(n, 51)
+    outs = [_adjoint_gpu(B, dev, pos, vel, mass, gx, gv, S, K, prec)
+            for K in (1, 3, 5, 12, 50)]
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_adjoint_zero_steps_is_vjp(B, dev, prec):
+    say("adjoint zero steps", prec)
+    n = 333
+    pos, vel, mass = inputs.uniform_cube(n, 52)
+    gx = inputs.upstream_normal(n, 53)
+    gv = inputs.upstream_normal(n, 54)
+    ga = inputs.upstream_normal(n, 55)
+    ox, ov, om = _adjoint_gpu(B, dev, pos, vel, mass, gx, gv, 0, 3, prec, ga)
+    vx, vm = B.nbody_accel_vjp(T(pos, dev), T(mass, dev), T(ga, dev), 1.0, 1e-3, prec)
+    assert np.array_equal(ov, gv)
+    assert np.array_equal(ox, gx + N(vx)) and np.array_equal(om, N(vm))
+
+
+# ------------------------------------------------------------- autograd ---
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_d64"])
+def test_autograd_accel(B, dev, oracle, prec):
+    say("autograd accel", prec)
+    from paper_2203_08263_amd import accel
+    n = 500
+    pos, _, mass = inputs.uniform_cube(n, 56)
+    g = inputs.upstream_normal(n, 57)
+    P = T(pos, dev).requires_grad_(True)
+    M = T(mass, dev).requires_grad_(True)
+    a = accel(P, M, 1.0, 1e-3, prec)
+    (a * T(g, dev)).sum().backward()
+    rx, rm = oracle.accel_vjp(pos, mass, g, 1.0, 1e-3)
+    bx, bm = _tol.vjp_bound(pos, mass, g, 1.0, 1e-3, prec)
+    _check_bound(N(P.grad), rx, bx, "grad x")
+    assert np.all(np.abs(N(M.grad) - rm) <= bm)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autograd_rollout(B, dev, oracle, prec):
+    say("autograd rollout", prec)
+    from paper_2203_08263_amd import rollout
+    n, S, K = 256, 9, 4
+    pos, vel, mass = inputs.uniform_cube(n, 58)
+    tgt = inputs.uniform_cube(n, 59)[0]
+    P = T(pos, dev).requires_grad_(True)
+    V = T(vel, dev).requires_grad_(True)
+    M = T(mass, dev).requires_grad_(True)
+    xS, vS, aS = rollout(P, V, M, 1.0, 1e-3, 1e-3, S, K, prec)
+    loss = ((xS - T(tgt, dev)) ** 2).sum()
+    loss.backward()
+    x_o, _, _ = oracle.step(pos, vel, mass, 1.0, 1e-3, 1e-3, S)
+    rx, rv, rm = oracle.step_adjoint(pos, vel, mass, 1.0, 1e-3, 1e-3, S,
+                                     2 * (x_o - tgt), np.zeros((3, n)))
+    if prec == "fp64":
+        for got, ref in ((P.grad, rx), (V.grad, rv), (M.grad, rm)):
+            assert np.linalg.norm(N(got) - ref) / np.linalg.norm(ref) <= 1e-12
+    else:
+        # the GPU's upstream 2 (x_S - tgt) uses its own mixed trajectory; its
+        # difference from the oracle's is bounded as in test_step_parity_small
+        ab = _tol.accel_bound(pos, mass, 1.0, 1e-3, prec).max()
+        dxs = 2 * 2 * S * S * 1e-6 * ab
+        bx, bv, bm = _tol.adjoint_bound(oracle, pos, vel, mass, 1.0, 1e-3, 1e-3,
+                                        S, 2 * (x_o - tgt), np.zeros((3, n)),
+                                        None, prec)
+        _check_bound(N(P.grad), rx, bx + np.sqrt(3) * dxs, "grad x0")
+        _check_bound(N(V.grad), rv, bv + np.sqrt(3) * dxs * S * 1e-3 * 2, "grad v0")
+        assert np.all(np.abs(N(M.grad) - rm) <= bm + 1e-6 * np.abs(rm).max())

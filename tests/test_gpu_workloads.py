@@ -1,0 +1,281 @@
+"""GPU parity at the five full-size workloads (paper section 4.1 sizes).
+
+Each workload runs at its full size in the launch configuration the library
+uses for that size; outputs are compared with the FP64 oracle on seeded
+sampled rows (the oracle evaluates rows one by one, O(rows * N)), element by
+element inside the bounds of tests/_tol.py, and the summary errors
+(E_max, E_norm, E_inf, E_med; normwise state errors; energy drift) are
+printed for the record.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import _tol
+from paper_2203_08263_amd import inputs, metrics
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+W = inputs.WORKLOADS
+PRECS = ["fp64", "mixed", "mixed_d64"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_08263_amd import binding
+    binding.load_library()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def dev(B):
+    return torch.device("cuda:0")
+
+
+def T(a, dev):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def N(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _check_bound(got, ref, bound, what):
+    err = np.sqrt(((got - ref) ** 2).sum(axis=0))
+    worst = int(np.argmax(err / np.maximum(bound, 1e-300)))
+    assert np.all(err <= bound), "%s: row %d err %.3e bound %.3e" % (
+        what, worst, err[worst], bound[worst])
+
+
+def _errs(got, ref):
+    e = metrics.rel_errors(got, ref)
+    return "E_max %.2e E_norm %.2e E_inf %.2e E_med %.2e" % (
+        e["E_max"], e["E_norm"], e["E_inf"], e["E_med"])
+
+
+# ------------------------------------------------- N = 1024, 100 steps FP64 --
+
+def test_cube1024_fp64_rollout(B, dev, oracle):
+    w = W["cube1024_fp64"]
+    say("workload", w)
+    pos, vel, mass = w.initial_state()
+    P, V, M = T(pos, dev), T(vel, dev), T(mass, dev)
+    A = torch.empty_like(P)
+    B.nbody_step(P, V, A, M, w.G, w.eps, w.dt, w.steps, "fp64")
+    x, v, a = oracle.step(pos, vel, mass, w.G, w.eps, w.dt, w.steps)
+    ex, ev = metrics.normwise(N(P), x), metrics.normwise(N(V), v)
+    e0 = sum(oracle.energy(pos, vel, mass, w.G, w.eps))
+    e1 = sum(oracle.energy(N(P), N(V), mass, w.G, w.eps))
+    say("  fp64 final state err x %.2e v %.2e; acc %s; energy drift %.2e"
+        % (ex, ev, _errs(N(A), a), abs(e1 - e0) / abs(e0)))
+    assert ex <= 1e-12 and ev <= 1e-12
+    _check_bound(N(A), oracle.accel(N(P), mass, w.G, w.eps),
+                 _tol.accel_bound(N(P), mass, w.G, w.eps, "fp64"), "final acc")
+
+
+# -------------------------------------- N = 16384, FP64 vs mixed, 10 steps --
+
+@pytest.fixture(scope="module")
+def cube16384(oracle):
+    w = W["cube16384"]
+    pos, vel, mass = w.initial_state()
+    a0 = oracle.accel(pos, mass, w.G, w.eps)
+    xS, vS, aS = oracle.step(pos, vel, mass, w.G, w.eps, w.dt, w.steps)
+    return w, pos, vel, mass, a0, (xS, vS, aS)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_cube16384_accel(B, dev, cube16384, prec):
+    w, pos, vel, mass, a0, _ = cube16384
+    say("workload", w.name, prec, "acceleration at x0")
+    got = N(B.nbody_accel(T(pos, dev), T(mass, dev), w.G, w.eps, prec))
+    say("  all rows: " + _errs(got, a0))
+    rows = w.rows(2048)
+    _check_bound(got[:, rows], a0[:, rows],
+                 _tol.accel_bound(pos, mass, w.G, w.eps, prec, rows), prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_cube16384_rollout(B, dev, oracle, cube16384, prec):
+    w, pos, vel, mass, _, (xS, vS, aS) = cube16384
+    say("workload", w.name, prec, "rollout")
+    P, V, M = T(pos, dev), T(vel, dev), T(mass, dev)
+    A = torch.empty_like(P)
+    B.nbody_step(P, V, A, M, w.G, w.eps, w.dt, w.steps, prec)
+    x, v, a = N(P), N(V), N(A)
+    ex, ev = metrics.normwise(x, xS), metrics.normwise(v, vS)
+    e0 = sum(oracle.energy(pos, vel, mass, w.G, w.eps))
+    e1 = sum(oracle.energy(x, v, mass, w.G, w.eps))
+    say("  final state err x %.2e v %.2e; energy drift %.2e" % (ex, ev, abs(e1 - e0) / abs(e0)))
+    if prec == "fp64":
+        assert ex <= 1e-12 and ev <= 1e-12
+    else:
+        ab = _tol.accel_bound(pos, mass, w.G, w.eps, prec, w.rows(512)).max()
+        # per-step velocity error <= dt * accel bound (no chaotic growth in
+        # 10 steps of 1e-3): the bound over rows is sampled, so use 4x margin
+        assert np.abs(v - vS).max() <= 4 * w.steps * w.dt * ab
+        assert np.abs(x - xS).max() <= 4 * w.steps ** 2 * w.dt ** 2 * ab
+
+
+# ---------------------------------------- N = 65536 Plummer, mixed, 10 steps --
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_plummer65536(B, dev, oracle, prec):
+    w = W["plummer65536"]
+    say("workload", w.name, prec)
+    pos, vel, mass = w.initial_state()
+    rows = w.rows(4096)
+    P, V, M = T(pos, dev), T(vel, dev), T(mass, dev)
+    a0 = N(B.nbody_accel(P, M, w.G, w.eps, prec))
+    r0 = oracle.accel_rows(pos, mass, w.G, w.eps, rows)
+    say("  x0, 4096 rows: " + _errs(a0[:, rows], r0))
+    _check_bound(a0[:, rows], r0, _tol.accel_bound(pos, mass, w.G, w.eps, prec, rows),
+                 "x0")
+    A = torch.empty_like(P)
+    t0 = time.time()
+    B.nbody_step(P, V, A, M, w.G, w.eps, w.dt, w.steps, prec)
+    torch.cuda.synchronize()
+    say("  rollout %.1f ms" % (1e3 * (time.time() - t0)))
+    x = N(P)
+    rS = oracle.accel_rows(x, mass, w.G, w.eps, rows)
+    aS = N(A)[:, rows]
+    say("  x_S (GPU positions), 4096 rows: " + _errs(aS, rS))
+    _check_bound(aS, rS, _tol.accel_bound(x, mass, w.G, w.eps, prec, rows), "x_S")
+
+
+# ------------------------------- N = 8192, 50 steps, adjoint with K = 10 ----
+
+@pytest.fixture(scope="module")
+def adjoint8192(oracle):
+    w = W["cube8192_adjoint"]
+    pos, vel, mass = w.initial_state()
+    dv = inputs._rng(w.seed + 300).normal(0.0, 1e-3, size=(3, w.n))
+    target, _, _ = oracle.step(pos, vel + dv, mass, w.G, w.eps, w.dt, w.steps)
+    xS, _, _ = oracle.step(pos, vel, mass, w.G, w.eps, w.dt, w.steps)
+    gx = 2.0 * (xS - target)
+    rx, rv, rm = oracle.step_adjoint(pos, vel, mass, w.G, w.eps, w.dt, w.steps,
+                                     gx, np.zeros_like(gx))
+    return w, pos, vel, mass, target, (rx, rv, rm)
+
+
+def _gpu_loss_and_grad(B, dev, w, pos, vel, mass, target, prec):
+    P, V, M = T(pos, dev), T(vel, dev), T(mass, dev)
+    A = torch.empty_like(P)
+    ck = torch.empty(B.nbody_checkpoint_bytes(w.n, w.steps, w.ckpt_every) // 8,
+                     dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    B.nbody_step(P, V, A, M, w.G, w.eps, w.dt, w.steps, prec, ckpt=ck,
+                 ckpt_every=w.ckpt_every)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    Tg = T(target, dev)
+    gx = 2.0 * (P - Tg)
+    gv = torch.zeros_like(gx)
+    _, _, gm = B.nbody_step_adjoint(ck, M, gx, gv, w.G, w.eps, w.dt, w.steps,
+                                    w.ckpt_every, prec)
+    torch.cuda.synchronize()
+    t2 = time.time()
+    loss = float(((P - Tg) ** 2).sum())
+    return loss, N(gx), N(gv), N(gm), (t1 - t0, t2 - t1)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_adjoint8192_vs_oracle(B, dev, oracle, adjoint8192, prec):
+    w, pos, vel, mass, target, (rx, rv, rm) = adjoint8192
+    say("workload", w.name, prec)
+    _, gx, gv, gm, (tf, tb) = _gpu_loss_and_grad(B, dev, w, pos, vel, mass, target, prec)
+    ev, em, ex = (metrics.normwise(gv, rv), metrics.normwise(gm, rm),
+                  metrics.normwise(gx, rx))
+    say("  grad err vs FP64 adjoint: v0 %.2e m %.2e x0 %.2e; t_fwd %.1f ms "
+        "t_bwd %.1f ms (wall)" % (ev, em, ex, 1e3 * tf, 1e3 * tb))
+    if prec == "fp64":
+        assert max(ev, em, ex) <= 1e-10
+        return
+    rows = w.rows(64)
+    xS, _, _ = oracle.step(pos, vel, mass, w.G, w.eps, w.dt, w.steps)
+    bx, bv, bm = _tol.adjoint_bound(oracle, pos, vel, mass, w.G, w.eps, w.dt,
+                                    w.steps, 2.0 * (xS - target),
+                                    np.zeros((3, w.n)), None, prec, rows)
+    # the upstream gradient 2 (x_S - target) is taken on the GPU's own mixed
+    # trajectory; its difference from the oracle's x_S adds at most
+    # 2 |dx_S| (4 S^2 dt^2 max accel bound) times the sweep's gain (< 2)
+    ab = _tol.accel_bound(pos, mass, w.G, w.eps, prec, w.rows(256)).max()
+    slack = 2 * 2 * 4 * w.steps ** 2 * w.dt ** 2 * ab
+    _check_bound(gv[:, rows], rv[:, rows], bv + slack * w.steps * w.dt, "dL/dv0")
+    _check_bound(gx[:, rows], rx[:, rows], bx + slack, "dL/dx0")
+    assert np.all(np.abs(gm[rows] - rm[rows]) <= bm + slack * np.abs(rm).max())
+
+
+def test_adjoint8192_central_fd(B, dev, adjoint8192):
+    # Central differences (h = 1e-6) of the FP64 GPU rollout on 16 seeded
+    # velocity coordinates and 16 seeded masses.
+    w, pos, vel, mass, target, _ = adjoint8192
+    say("workload", w.name, "central FD")
+    _, _, gv, gm, _ = _gpu_loss_and_grad(B, dev, w, pos, vel, mass, target, "fp64")
+    rng = inputs._rng(w.seed + 200)
+    vc = [(int(c), int(i)) for c, i in zip(rng.integers(0, 3, 16),
+                                            rng.choice(w.n, 16, replace=False))]
+    mi = [int(i) for i in rng.choice(w.n, 16, replace=False)]
+    h = 1e-6
+
+    def loss(p, v, m):
+        P, V, M = T(p, dev), T(v, dev), T(m, dev)
+        A = torch.empty_like(P)
+        B.nbody_step(P, V, A, M, w.G, w.eps, w.dt, w.steps, "fp64")
+        return float(((P - T(target, dev)) ** 2).sum())
+
+    worst = 0.0
+    for c, i in vc:
+        vp, vm_ = vel.copy(), vel.copy()
+        vp[c, i] += h
+        vm_[c, i] -= h
+        fd = (loss(pos, vp, mass) - loss(pos, vm_, mass)) / (2 * h)
+        worst = max(worst, abs(fd - gv[c, i]) / max(abs(gv[c, i]), 1e-8))
+        assert fd == pytest.approx(gv[c, i], rel=1e-5, abs=1e-9)
+    for i in mi:
+        mp, mm = mass.copy(), mass.copy()
+        mp[i] += h
+        mm[i] -= h
+        fd = (loss(pos, vel, mp) - loss(pos, vel, mm)) / (2 * h)
+        worst = max(worst, abs(fd - gm[i]) / max(abs(gm[i]), 1e-8))
+        assert fd == pytest.approx(gm[i], rel=1e-5, abs=1e-7)
+    say("  worst relative FD disagreement %.2e" % worst)
+
+
+# --------------------------- N = 262144 Plummer a = 0.1, accel + VJP (mixed) --
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_plummer262144_accel_vjp(B, dev, oracle, prec):
+    w = W["plummer262144_vjp"]
+    say("workload", w.name, prec)
+    pos, _, mass = w.initial_state()
+    g = inputs.upstream_normal(w.n, w.seed + 400)
+    rows = w.rows(1024)
+    P, M, Gt = T(pos, dev), T(mass, dev), T(g, dev)
+    a = N(B.nbody_accel(P, M, w.G, w.eps, prec))[:, rows]
+    gx, gm = B.nbody_accel_vjp(P, M, Gt, w.G, w.eps, prec)
+    gx, gm = N(gx)[:, rows], N(gm)[rows]
+    ra = oracle.accel_rows(pos, mass, w.G, w.eps, rows)
+    rx, rm = oracle.accel_vjp_rows(pos, mass, g, w.G, w.eps, rows)
+    say("  accel 1024 rows: " + _errs(a, ra))
+    say("  vjp dL/dx 1024 rows: " + _errs(gx, rx))
+    say("  vjp dL/dm 1024 rows: max rel %.2e" % float(np.max(np.abs(gm - rm) / np.abs(rm))))
+    brow = rows[:256]
+    sel = np.searchsorted(rows, brow)
+    _check_bound(a[:, sel], ra[:, sel],
+                 _tol.accel_bound(pos, mass, w.G, w.eps, prec, brow), "accel")
+    bx, bm = _tol.vjp_bound(pos, mass, g, w.G, w.eps, prec, brow)
+    _check_bound(gx[:, sel], rx[:, sel], bx, "dL/dx")
+    assert np.all(np.abs(gm[sel] - rm[sel]) <= bm), "dL/dm"
