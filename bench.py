@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Benchmark of the all-pairs N-body hot path on one MI355X.
+
+Workload: 16384 bodies in a uniform cube (positions U(-1,1)^3, velocities
+N(0, 0.1^2), masses U(0.5,1)/N), G = 1, Plummer softening eps = 1e-3,
+dt = 1e-3, 10 kick-drift-kick steps -- the FP64-vs-mixed configuration.
+One benchmark step is one pass of the whole hot path over that input:
+
+  * forward: 10 KDK steps (nbody_step, acceleration of x_0 already cached)
+    writing a checkpoint every 5 steps;
+  * reverse: nbody_step_adjoint for a seeded upstream dL/dx_10 ~ N(0,1)
+    (segment recomputation from the checkpoints plus 11 VJPs).
+
+`value` = N^2 * 10 / (forward + adjoint time) in G body-pair interactions/s
+(the paper's convention, section 4.1: N^2 pairs per force evaluation, self
+pairs included, 20 flops per pair).  Inputs are resident in HBM before the
+timed region; every step restores the initial state with device copies.
+
+Also reported on the same line: forward-only and FP64 / mixed-D64 legs, the
+roofline position of the dominant kernel (timed with HIP events on the
+stream it runs on), the stated errors against the FP64 oracle, and the
+oracle itself timed on the host cores (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("G body-pair interactions/s (FP64 vs mixed, fwd and fwd+adjoint) "
+          "at stated error")
+WORKLOAD = "cube16384"
+CKPT_EVERY = 5
+PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32, published
+PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64, published
+FLOPS_PER_PAIR = {"accel": 20, "vjp": 48}   # counting rule: the design doc
+DTYPE = {"fp64": "f64", "mixed": "f32-pair/f64-acc",
+         "mixed_d64": "f32-pair(f64-diff)/f64-acc"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Bench:
+    def __init__(self, torch, B, inputs, w):
+        self.torch, self.B, self.w = torch, B, w
+        dev = torch.device("cuda:0")
+        self.dev = dev
+        T = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa
+        pos, vel, mass = w.initial_state()
+        self.np_state = (pos, vel, mass)
+        self.gx_T = inputs.upstream_normal(w.n, w.seed + 500)
+        self.P0, self.V0, self.M = T(pos), T(vel), T(mass)
+        self.GX0 = T(self.gx_T)
+        n = w.n
+        self.P, self.V = torch.empty_like(self.P0), torch.empty_like(self.V0)
+        self.A = torch.empty_like(self.P0)
+        self.GX, self.GV = torch.empty_like(self.P0), torch.empty_like(self.P0)
+        self.GM = torch.empty_like(self.M)
+        self.CK = torch.empty(B.nbody_checkpoint_bytes(n, w.steps, CKPT_EVERY) // 8,
+                              dtype=torch.float64, device=dev)
+        self.A0 = {}
+        self.ws = {}
+        for p in ("fp64", "mixed", "mixed_d64"):
+            self.A0[p] = B.nbody_accel(self.P0, self.M, w.G, w.eps, p)
+            nb = max(B.nbody_workspace_bytes(B.NBODY_OP_STEP, n, w.steps, CKPT_EVERY, p),
+                     B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, n, w.steps,
+                                             CKPT_EVERY, p), 256)
+            self.ws[p] = torch.empty(nb, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+
+    def forward(self, p):
+        w, B = self.w, self.B
+        self.P.copy_(self.P0)
+        self.V.copy_(self.V0)
+        self.A.copy_(self.A0[p])
+        B.nbody_step(self.P, self.V, self.A, self.M, w.G, w.eps, w.dt, w.steps, p,
+                     acc_valid=True, ckpt=self.CK, ckpt_every=CKPT_EVERY,
+                     workspace=self.ws[p])
+
+    def adjoint(self, p):
+        w, B = self.w, self.B
+        self.GX.copy_(self.GX0)
+        self.GV.zero_()
+        B.nbody_step_adjoint(self.CK, self.M, self.GX, self.GV, w.G, w.eps, w.dt,
+                             w.steps, CKPT_EVERY, p, gmass=self.GM,
+                             workspace=self.ws[p])
+
+    def step(self, p):
+        self.forward(p)
+        self.adjoint(p)
+
+    def timed(self, fn, reps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return e0.elapsed_time(e1) / reps, 1e3 * wall / reps
+
+
+def roofline(bench, p, kind):
+    """Average launch duration (HIP events on the launch stream) of the
+    all-pairs kernel of `kind` at the workload's size, and its position
+    against the vector peak of its arithmetic type."""
+    torch, B, w = bench.torch, bench.B, bench.w
+    n = w.n
+    if kind == "accel":
+        fn = lambda: B.nbody_accel(bench.P0, bench.M, w.G, w.eps, p, out=bench.A)  # noqa
+    else:
+        fn = lambda: B.nbody_accel_vjp(bench.P0, bench.M, bench.GX0, w.G, w.eps, p,  # noqa
+                                       gpos=bench.GX, gmass=bench.GM)
+    ms, _ = bench.timed(fn, reps=50, warmup=3)
+    flops = FLOPS_PER_PAIR[kind] * n * n
+    achieved = flops / (ms * 1e-3) / 1e12
+    peak = PEAK_FP64_TFLOPS if p == "fp64" else PEAK_FP32_TFLOPS
+    return {"kernel": "%s (%s), N=%d" % ({"accel": "accel_kernel", "vjp": "vjp_kernel"}[kind],
+                                         p, n),
+            "bound": "alu", "achieved": round(achieved, 2), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "avg_launch_ms": round(ms, 4),
+            "flops_per_pair": FLOPS_PER_PAIR[kind]}
+
+
+def cpu_baseline(bench, p, gx_gpu, gv_gpu, gm_gpu):
+    """The FP64 oracle on the host cores over the same workload (forward plus
+    exact reverse sweep), and the stated errors of the GPU results."""
+    import numpy as np
+
+    import oracle
+    from paper_2203_08263_amd import metrics
+
+    w = bench.w
+    pos, vel, mass = bench.np_state
+    n = w.n
+    t0 = time.perf_counter()
+    rx, rv, rm = oracle.step_adjoint(pos, vel, mass, w.G, w.eps, w.dt, w.steps,
+                                     bench.gx_T, np.zeros((3, n)))
+    t_cpu = time.perf_counter() - t0
+    base = {"value": round(n * n * w.steps / t_cpu / 1e9, 4),
+            "unit": "G interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "the whole workload: N=%d, %d KDK steps forward + exact "
+                      "reverse sweep (FP64, all positions stored), %.1f s"
+                      % (n, w.steps, t_cpu)}
+    # stated errors: gradients of this run vs the oracle's; accelerations at
+    # x_0 on 2048 seeded rows for every precision
+    err = {"grad_vs_oracle_normwise_%s" % p: {
+        "dL/dx0": metrics.normwise(gx_gpu, rx), "dL/dv0": metrics.normwise(gv_gpu, rv),
+        "dL/dm": metrics.normwise(gm_gpu, rm)}}
+    rows = w.rows(2048)
+    ref = oracle.accel_rows(pos, mass, w.G, w.eps, rows)
+    for q in ("fp64", "mixed", "mixed_d64"):
+        a = bench.A0[q].cpu().numpy()[:, rows]
+        err["accel_x0_2048rows_%s" % q] = {k: float("%.3e" % v) for k, v in
+                                          metrics.rel_errors(a, ref).items()}
+    return base, err
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed steps")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="mixed",
+                    choices=["fp64", "mixed", "mixed_d64"])
+    ap.add_argument("--no-legs", action="store_true",
+                    help="time only the main precision's forward + adjoint")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU "
+              "path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2203_08263_amd import binding as B
+    from paper_2203_08263_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    B.load_library()
+    w = inputs.WORKLOADS[WORKLOAD]
+    bench = Bench(torch, B, inputs, w)
+    p = args.precision
+    n2s = float(w.n) * w.n * w.steps
+
+    # main timed region: K whole steps of the hot path
+    log("bench: %s, precision %s, %d warmup + %d timed steps" % (w.name, p,
+                                                                args.warmup, args.steps))
+    torch.cuda.synchronize()   # one process, one GPU: no barrier to take
+    ms, wall_ms = bench.timed(lambda: bench.step(p), args.steps, args.warmup)
+    value = n2s / (ms * 1e-3) / 1e9
+    log("bench: %.3f ms/step (events), %.3f ms/step (wall), %.1f G int/s"
+        % (ms, wall_ms, value))
+    gx, gv, gm = (bench.GX.cpu().numpy(), bench.GV.cpu().numpy(),
+                  bench.GM.cpu().numpy())
+
+    legs = {}
+    if not args.no_legs:
+        for q in ("fp64", "mixed", "mixed_d64"):
+            fms, _ = bench.timed(lambda: bench.forward(q), 10, 2)
+            sms, _ = bench.timed(lambda: bench.step(q), 5, 1)
+            legs[q] = {"fwd_G_int_s": round(n2s / (fms * 1e-3) / 1e9, 1),
+                       "fwd_ms": round(fms, 4),
+                       "fwd_adj_G_int_s": round(n2s / (sms * 1e-3) / 1e9, 1),
+                       "fwd_adj_ms": round(sms, 4),
+                       "bwd_over_fwd": round((sms - fms) / fms, 3)}
+            log("bench: leg %s %s" % (q, legs[q]))
+
+    # roofline of the dominant kernel of the step (the VJP: 11 launches of
+    # ~2x the cost of each of the 18 force evaluations), plus the forward's
+    roof = roofline(bench, p, "vjp")
+    roof_fwd = roofline(bench, p, "accel")
+    log("bench: roofline vjp %s" % roof)
+    log("bench: roofline accel %s" % roof_fwd)
+
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "G interactions/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[p],
+           "data": "synthetic",
+           "config": {"workload": "%s: N=%d uniform cube, %d KDK steps forward + "
+                                  "checkpointed adjoint (every %d), eps=%g, dt=%g, "
+                                  "G=%g, precision %s"
+                                  % (w.name, w.n, w.steps, CKPT_EVERY, w.eps, w.dt,
+                                     w.G, p),
+                      "n": w.n, "sim_steps": w.steps, "ckpt_every": CKPT_EVERY,
+                      "precision": p, "parallelism": "single GPU"},
+           "roofline": roof, "roofline_forward": roof_fwd, "legs": legs}
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (FP64 oracle on the host cores)")
+        base, err = cpu_baseline(bench, p, gx, gv, gm)
+        out["cpu_baseline"] = base
+        out["error"] = err
+    else:
+        out["cpu_baseline"] = None
+    _ = np
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

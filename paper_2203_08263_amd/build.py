@@ -15,6 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnbody_hip.so")
 SOURCES = ["nbody_kernels.hip", "nbody_api.hip"]
+MICROBENCH = os.path.join(HERE, "valu_microbench")
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -47,5 +48,21 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_microbench(verbose: bool = False) -> str:
+    """The VALU issue-rate microbenchmark (a standalone gfx950 executable)."""
+    flags = [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")]
+    tmp = MICROBENCH + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), *flags, os.path.join(CSRC, "valu_microbench.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed building valu_microbench")
+    os.replace(tmp, MICROBENCH)
+    return MICROBENCH
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_microbench(verbose=True))
