@@ -39,7 +39,18 @@ WORKLOAD = "cube16384"
 CKPT_EVERY = 5
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32, published
 PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64, published
-FLOPS_PER_PAIR = {"accel": 20, "vjp": 48}   # counting rule: the design doc
+# Flops per body pair, counting add/sub/mul as 1, FMA as 2 and the reciprocal
+# square root as 2: the force pair (3 sub, 3 FMA, rsqrt, 3 mul, 3 FMA) is the
+# paper's 20; the VJP pair (3 sub, 3 FMA, rsqrt, 2 mul, 3 mul + 3 FMA for h,
+# 1 mul + 2 FMA twice for e.h and gbar.e, 1 FMA, 2 mul, 6 FMA) is 48.
+FLOPS_PER_PAIR = {"accel": 20, "vjp": 48}
+# HBM bytes per launch of the roofline kernel from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, each scaled by what the counter reads for a
+# 64 MiB device copy; profiles/vjp_kernel_cube16384_mixed_traffic.md).  They
+# describe the kernel source they were taken on (first 16 hex digits of its
+# SHA-256) and are reported as null for any other source.
+MEASURED_TRAFFIC = {("vjp", "mixed"): {"bytes": 24.2e6, "src_sha256": "67cc9fe81b02bdb6"}}
+KERNEL_SRC = os.path.join(ROOT, "paper_2203_08263_amd", "csrc", "nbody_kernels.hip")
 DTYPE = {"fp64": "f64", "mixed": "f32-pair/f64-acc",
          "mixed_d64": "f32-pair(f64-diff)/f64-acc"}
 
@@ -127,12 +138,20 @@ def roofline(bench, p, kind):
                                        gpos=bench.GX, gmass=bench.GM)
     ms, _ = bench.timed(fn, reps=50, warmup=3)
     flops = FLOPS_PER_PAIR[kind] * n * n
+    traffic = None
+    rec = MEASURED_TRAFFIC.get((kind, p))
+    if rec is not None:
+        import hashlib
+        with open(KERNEL_SRC, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] == rec["src_sha256"]:
+                traffic = rec["bytes"]
     achieved = flops / (ms * 1e-3) / 1e12
     peak = PEAK_FP64_TFLOPS if p == "fp64" else PEAK_FP32_TFLOPS
     return {"kernel": "%s (%s), N=%d" % ({"accel": "accel_kernel", "vjp": "vjp_kernel"}[kind],
                                          p, n),
             "bound": "alu", "achieved": round(achieved, 2), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch",
             "avg_launch_ms": round(ms, 4),
             "flops_per_pair": FLOPS_PER_PAIR[kind]}
 
@@ -182,6 +201,10 @@ def main(argv=None):
     ap.add_argument("--no-legs", action="store_true",
                     help="time only the main precision's forward + adjoint")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", choices=["accel", "vjp"], default=None,
+                    help="counter-collection mode: a 64 MiB device copy (the "
+                         "traffic calibration) then --steps launches of one "
+                         "all-pairs kernel at the workload size; no JSON line")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -203,6 +226,22 @@ def main(argv=None):
     bench = Bench(torch, B, inputs, w)
     p = args.precision
     n2s = float(w.n) * w.n * w.steps
+
+    if args.profile:
+        src = torch.ones(8 << 20, dtype=torch.float64, device=bench.dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)                       # calibration: 64 MiB read + write
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            if args.profile == "accel":
+                B.nbody_accel(bench.P0, bench.M, w.G, w.eps, p, out=bench.A)
+            else:
+                B.nbody_accel_vjp(bench.P0, bench.M, bench.GX0, w.G, w.eps, p,
+                                  gpos=bench.GX, gmass=bench.GM)
+        torch.cuda.synchronize()
+        log("bench: profile mode done (%s, %s, %d launches)" % (args.profile, p,
+                                                                 args.steps))
+        return 0
 
     # main timed region: K whole steps of the hot path
     log("bench: %s, precision %s, %d warmup + %d timed steps" % (w.name, p,

@@ -11,12 +11,14 @@ namespace nbody {
 // Threads per workgroup of every kernel (4 wave64s) and bodies per LDS tile.
 constexpr int kThreads = 256;
 
-// Launch plan of one all-pairs kernel: R target bodies per thread, n_ib
-// target blocks of kThreads*R bodies, sj source splits of jchunk bodies
-// (jchunk a multiple of kThreads).  Depends only on (kind, precision, n), so
-// a recomputation reproduces every partial sum bitwise.
+// Launch plan of one all-pairs kernel: L lanes share each target body and
+// each lane group serves R targets, so a workgroup owns (kThreads/L)*R
+// targets; n_ib target blocks; sj source splits of jchunk bodies (jchunk a
+// multiple of kThreads).  Depends only on (kind, precision, n), so a
+// recomputation reproduces every partial sum bitwise.
 struct Plan {
   int R;
+  int L;
   int64_t n_ib;
   int64_t sj;
   int64_t jchunk;

@@ -23,6 +23,8 @@
 // section 3.2 / 3.3 listings) with the acceleration taken directly as
 // G sum_j m_j d s^-3/2 and the reciprocal square root from the hardware
 // approximation (v_rsq_f32 / v_rsq_f64), refined by Newton's method in FP64.
+#include <algorithm>
+
 #include "nbody_internal.h"
 #include "../../include/nbody.h"
 
@@ -77,19 +79,13 @@ __device__ __forceinline__ void pair_f32(float dx, float dy, float dz, float m,
   az = fmaf(w, dz, az);
 }
 
-// h = a b - c d as the difference of two separately rounded products, so
-// that it is exactly antisymmetric under (a,b) <-> (c,d) and exactly zero for
-// the self pair j == k.  (A fused a*b - c*d leaves the rounding error of c*d,
-// which the self pair multiplies by eps^-3.)
-template <typename T>
-__device__ __forceinline__ T diff_of_products(T a, T b, T c, T d) {
-#pragma clang fp contract(off)
-  return a * b - c * d;
-}
-
 // One source j against target k for the VJP (row formulation):
 //   g += s^-3/2 (h + t e),  t = -3 (e.h) / s,   dm += (gbar_j . e) s^-3/2
-// with e = x_j - x_k and h = m_k gbar_j - m_j gbar_k.
+// with e = x_j - x_k and h = m_k gbar_j - m_j gbar_k, formed as
+// fma(m_k, gbar_j, -(m_j gbar_k)).  For the self pair j == k that h is not
+// zero but the exact rounding error delta of m_k gbar_k, and since e = 0 the
+// pair adds exactly fma(y3_self, delta, g): see self_pair_term, which the
+// kernel subtracts afterwards so the self pair contributes nothing.
 template <typename T>
 __device__ __forceinline__ void vjp_pair(T ex, T ey, T ez, T mj, T gjx, T gjy,
                                          T gjz, T mk, T gkx, T gky, T gkz,
@@ -101,9 +97,9 @@ __device__ __forceinline__ void vjp_pair(T ex, T ey, T ez, T mj, T gjx, T gjy,
   if constexpr (sizeof(T) == 8) y = rsqrt_f64(s); else y = rsqrt_f32(s);
   const T y2 = y * y;
   const T y3 = y2 * y;
-  const T hx = diff_of_products(mk, gjx, mj, gkx);
-  const T hy = diff_of_products(mk, gjy, mj, gky);
-  const T hz = diff_of_products(mk, gjz, mj, gkz);
+  const T hx = fma(mk, gjx, -(mj * gkx));
+  const T hy = fma(mk, gjy, -(mj * gky));
+  const T hz = fma(mk, gjz, -(mj * gkz));
   const T eh = fma(ez, hz, fma(ey, hy, ex * hx));
   const T ge = fma(gjz, ez, fma(gjy, ey, gjx * ex));
   dm = fma(ge, y3, dm);
@@ -111,6 +107,21 @@ __device__ __forceinline__ void vjp_pair(T ex, T ey, T ez, T mj, T gjx, T gjy,
   gx = fma(y3, fma(t, ex, hx), gx);
   gy = fma(y3, fma(t, ey, hy), gy);
   gz = fma(y3, fma(t, ez, hz), gz);
+}
+
+// What vjp_pair adds to g for the self pair j == k (e = 0, s = eps^2): the
+// same y3 and h operations, evaluated once per target.  The product is
+// rounded like the pair's own fma(y3, delta, 0) (exact for FP32 operands);
+// contraction is off so the caller's subtraction cannot absorb it into an
+// FMA, which would leave the product's rounding error behind.
+template <typename T>
+__device__ __forceinline__ double self_pair_term(T mk, T gk, T eps2) {
+#pragma clang fp contract(off)
+  T y;
+  if constexpr (sizeof(T) == 8) y = rsqrt_f64(eps2); else y = rsqrt_f32(eps2);
+  const T y3 = (y * y) * y;
+  const T delta = fma(mk, gk, -(mk * gk));
+  return double(y3) * double(delta);
 }
 
 // ------------------------------------------------------ source tile layout --
@@ -147,19 +158,40 @@ template <int PREC> struct Coord { using T = double; using D = double; };
 template <> struct Coord<NBODY_MIXED> { using T = float; using D = float; };
 template <> struct Coord<NBODY_MIXED_D64> { using T = double; using D = float; };
 
-// ------------------------------------------------------------ acceleration --
+// Sum over the L consecutive lanes that share a target (L a power of two
+// dividing the wave size) by an xor butterfly: every stage adds the same two
+// values in both partner lanes, so all L lanes end with the bitwise same
+// total, in an order fixed by L alone.
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int m = 1; m < L; m <<= 1) v += __shfl_xor(v, m);
+  return v;
+}
 
-template <int PREC, int R>
+// ------------------------------------------------------------ acceleration --
+//
+// Thread t of a workgroup serves target group g = t / L with lane q = t % L;
+// the group owns R targets i = blockIdx.x * (256/L) * R + g + r * (256/L),
+// and lane q visits the tile entries q, q + L, q + 2L, ...  With L > 1 a
+// small system still yields enough waves without splitting the source range
+// into many FP64 partials.
+
+template <int PREC, int R, int L>
 __global__ __launch_bounds__(kThreads) void accel_kernel(
     int n, const double *__restrict__ pos, const double *__restrict__ mass,
     double eps2d, double scale, int jchunk, double *__restrict__ out,
     size_t split_stride) {
   using CT = typename Coord<PREC>::T;
   using DT = typename Coord<PREC>::D;
+  constexpr int G = kThreads / L;             // target groups per workgroup
+  constexpr int PER = kThreads / L;           // tile entries per lane
+  constexpr int C = PER < kChunk ? PER : kChunk;
   __shared__ Src<PREC> tile[kThreads];
 
   const int tid = threadIdx.x;
-  const int ibase = blockIdx.x * (kThreads * R) + tid;
+  const int g = tid / L, q = tid % L;
+  const int ibase = blockIdx.x * (G * R) + g;
   const int jbeg = blockIdx.y * jchunk;
   const int jend = min(n, jbeg + jchunk);
 
@@ -167,7 +199,7 @@ __global__ __launch_bounds__(kThreads) void accel_kernel(
   double ax[R], ay[R], az[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int i = ibase + r * kThreads;
+    const int i = ibase + r * G;
     const bool ok = i < n;
     xi[r] = ok ? CT(pos[i]) : CT(0);
     yi[r] = ok ? CT(pos[n + i]) : CT(0);
@@ -184,8 +216,8 @@ __global__ __launch_bounds__(kThreads) void accel_kernel(
 
     if constexpr (PREC == NBODY_FP64) {
 #pragma unroll 4
-      for (int u = 0; u < kThreads; ++u) {
-        const Src<PREC> s = tile[u];
+      for (int u = 0; u < PER; ++u) {
+        const Src<PREC> s = tile[u * L + q];
 #pragma unroll
         for (int r = 0; r < R; ++r)
           pair_f64(s.x - xi[r], s.y - yi[r], s.z - zi[r], s.m, eps2d, ax[r],
@@ -193,13 +225,13 @@ __global__ __launch_bounds__(kThreads) void accel_kernel(
       }
     } else {
       const float eps2 = float(eps2d);
-      for (int u0 = 0; u0 < kThreads; u0 += kChunk) {
+      for (int u0 = 0; u0 < PER; u0 += C) {
         float fx[R], fy[R], fz[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) fx[r] = fy[r] = fz[r] = 0.0f;
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-          const Src<PREC> s = tile[u0 + u];
+        for (int u = 0; u < C; ++u) {
+          const Src<PREC> s = tile[(u0 + u) * L + q];
 #pragma unroll
           for (int r = 0; r < R; ++r)
             pair_f32(DT(s.x - xi[r]), DT(s.y - yi[r]), DT(s.z - zi[r]), s.m,
@@ -218,18 +250,21 @@ __global__ __launch_bounds__(kThreads) void accel_kernel(
   double *o = out + size_t(blockIdx.y) * split_stride;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int i = ibase + r * kThreads;
-    if (i < n) {
-      o[i] = scale * ax[r];
-      o[n + i] = scale * ay[r];
-      o[2 * n + i] = scale * az[r];
+    const double sx = group_sum<L>(ax[r]);
+    const double sy = group_sum<L>(ay[r]);
+    const double sz = group_sum<L>(az[r]);
+    const int i = ibase + r * G;
+    if (q == 0 && i < n) {
+      o[i] = scale * sx;
+      o[n + i] = scale * sy;
+      o[2 * n + i] = scale * sz;
     }
   }
 }
 
 // ---------------------------------------------------------------------- VJP --
 
-template <int PREC, int R>
+template <int PREC, int R, int L>
 __global__ __launch_bounds__(kThreads) void vjp_kernel(
     int n, const double *__restrict__ pos, const double *__restrict__ mass,
     const double *__restrict__ gacc, double eps2d, double scale, int jchunk,
@@ -238,10 +273,14 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
   using CT = typename Coord<PREC>::T;
   using DT = typename Coord<PREC>::D;
   using AT = typename Coord<PREC>::D;  // arithmetic type of the pair terms
+  constexpr int G = kThreads / L;
+  constexpr int PER = kThreads / L;
+  constexpr int C = PER < kVjpChunk ? PER : kVjpChunk;
   __shared__ VSrc<PREC> tile[kThreads];
 
   const int tid = threadIdx.x;
-  const int kbase = blockIdx.x * (kThreads * R) + tid;
+  const int g = tid / L, q = tid % L;
+  const int kbase = blockIdx.x * (G * R) + g;
   const int jbeg = blockIdx.y * jchunk;
   const int jend = min(n, jbeg + jchunk);
 
@@ -250,7 +289,7 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
   double sx[R], sy[R], sz[R], sm[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int k = kbase + r * kThreads;
+    const int k = kbase + r * G;
     const bool ok = k < n;
     xk[r] = ok ? CT(pos[k]) : CT(0);
     yk[r] = ok ? CT(pos[n + k]) : CT(0);
@@ -280,8 +319,8 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
 
     if constexpr (PREC == NBODY_FP64) {
 #pragma unroll 2
-      for (int u = 0; u < kThreads; ++u) {
-        const VSrc<PREC> s = tile[u];
+      for (int u = 0; u < PER; ++u) {
+        const VSrc<PREC> s = tile[u * L + q];
 #pragma unroll
         for (int r = 0; r < R; ++r)
           vjp_pair<double>(s.x - xk[r], s.y - yk[r], s.z - zk[r], s.m, s.gx,
@@ -290,13 +329,13 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
       }
     } else {
       const float eps2 = float(eps2d);
-      for (int u0 = 0; u0 < kThreads; u0 += kVjpChunk) {
+      for (int u0 = 0; u0 < PER; u0 += C) {
         float fx[R], fy[R], fz[R], fm[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) fx[r] = fy[r] = fz[r] = fm[r] = 0.0f;
 #pragma unroll
-        for (int u = 0; u < kVjpChunk; ++u) {
-          const VSrc<PREC> s = tile[u0 + u];
+        for (int u = 0; u < C; ++u) {
+          const VSrc<PREC> s = tile[(u0 + u) * L + q];
 #pragma unroll
           for (int r = 0; r < R; ++r)
             vjp_pair<float>(DT(s.x - xk[r]), DT(s.y - yk[r]), DT(s.z - zk[r]),
@@ -316,105 +355,137 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
 
   double *ox = out_x + size_t(blockIdx.y) * split_stride;
   double *om = out_m + size_t(blockIdx.y) * split_stride;
+  const AT eps2a = AT(eps2d);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int k = kbase + r * kThreads;
-    if (k < n) {
-      ox[k] = scale * sx[r];
-      ox[n + k] = scale * sy[r];
-      ox[2 * n + k] = scale * sz[r];
-      om[k] = -scale * sm[r];
+    double tx = group_sum<L>(sx[r]);
+    double ty = group_sum<L>(sy[r]);
+    double tz = group_sum<L>(sz[r]);
+    const double tm = group_sum<L>(sm[r]);
+    const int k = kbase + r * G;
+    if (q == 0 && k < n) {
+      if (k >= jbeg && k < jend) {  // this split holds the self pair
+        tx -= self_pair_term<AT>(mk[r], gkx[r], eps2a);
+        ty -= self_pair_term<AT>(mk[r], gky[r], eps2a);
+        tz -= self_pair_term<AT>(mk[r], gkz[r], eps2a);
+      }
+      ox[k] = scale * tx;
+      ox[n + k] = scale * ty;
+      ox[2 * n + k] = scale * tz;
+      om[k] = -scale * tm;
     }
   }
 }
 
 // --------------------------------------------------- per-body FP64 kernels --
+//
+// One thread per (component, body): q = c * n + i.  The split partials of
+// one output are added in ascending split order; their loads are issued in
+// batches of 8 ahead of the (sequential) additions.
+
+constexpr int kBodyThreads = 64;
 
 __device__ __forceinline__ double split_sum(const double *__restrict__ part,
                                             size_t stride, int sj, size_t off) {
   double s = part[off];
-  for (int q = 1; q < sj; ++q) s += part[size_t(q) * stride + off];
+  int p = 1;
+  for (; p + 8 <= sj; p += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = part[size_t(p + k) * stride + off];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += v[k];
+  }
+  for (; p < sj; ++p) s += part[size_t(p) * stride + off];
   return s;
 }
 
-__global__ __launch_bounds__(kThreads) void reduce_kernel(
-    int n, int sj, const double *__restrict__ part, size_t stride, double G,
-    double *__restrict__ out_x, double *__restrict__ out_m) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-    out_x[size_t(c) * n + i] = G * split_sum(part, stride, sj, size_t(c) * n + i);
-  if (out_m) out_m[i] = G * split_sum(part, stride, sj, size_t(3) * n + i);
+__global__ __launch_bounds__(kBodyThreads) void reduce_kernel(
+    int n, int ncomp, int sj, const double *__restrict__ part, size_t stride,
+    double G, double *__restrict__ out_x, double *__restrict__ out_m) {
+  const size_t q = size_t(blockIdx.x) * kBodyThreads + threadIdx.x;
+  if (q >= size_t(ncomp) * n) return;
+  const double v = G * split_sum(part, stride, sj, q);
+  if (q < size_t(3) * n) out_x[q] = v;
+  else out_m[q - size_t(3) * n] = v;
 }
 
-__global__ __launch_bounds__(kThreads) void update_kernel(
+__global__ __launch_bounds__(kBodyThreads) void update_kernel(
     int n, int sj, const double *__restrict__ part, size_t stride, double G,
     const double *a_in, double *acc_out, const double *x_in, double *x_out,
     const double *v_in, double *v_out, double h, double dt, double *rec,
     unsigned flags) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const size_t q = size_t(c) * n + i;
-    const double a = part ? G * split_sum(part, stride, sj, q) : a_in[q];
-    const double x = x_in[q];
-    double v = v_in[q];
-    if (flags & kClose) v = v + h * a;
-    if (rec) {
-      rec[q] = x;
-      rec[size_t(3) * n + q] = v;
-      rec[size_t(6) * n + q] = a;
-    }
-    if (flags & kOpen) {
-      v = v + h * a;
-      x_out[q] = x + dt * v;
-    }
-    v_out[q] = v;
-    if (acc_out) acc_out[q] = a;
+  const size_t q = size_t(blockIdx.x) * kBodyThreads + threadIdx.x;
+  if (q >= size_t(3) * n) return;
+  const double a = part ? G * split_sum(part, stride, sj, q) : a_in[q];
+  const double x = x_in[q];
+  double v = v_in[q];
+  if (flags & kClose) v = v + h * a;
+  if (rec) {
+    rec[q] = x;
+    rec[size_t(3) * n + q] = v;
+    rec[size_t(6) * n + q] = a;
   }
+  if (flags & kOpen) {
+    v = v + h * a;
+    x_out[q] = x + dt * v;
+  }
+  v_out[q] = v;
+  if (acc_out) acc_out[q] = a;
 }
 
-__global__ __launch_bounds__(kThreads) void adj_init_kernel(
+__global__ __launch_bounds__(kBodyThreads) void adj_init_kernel(
     int n, const double *__restrict__ gvel, const double *__restrict__ gacc_T,
     double h, int add_hv, double *__restrict__ abar,
     double *__restrict__ gmass) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const size_t q = size_t(c) * n + i;
-    double ab = gacc_T ? gacc_T[q] : 0.0;
-    if (add_hv) ab = ab + h * gvel[q];
-    abar[q] = ab;
+  const size_t q = size_t(blockIdx.x) * kBodyThreads + threadIdx.x;
+  if (q >= size_t(4) * n) return;
+  if (q >= size_t(3) * n) {
+    gmass[q - size_t(3) * n] = 0.0;
+    return;
   }
-  gmass[i] = 0.0;
+  double ab = gacc_T ? gacc_T[q] : 0.0;
+  if (add_hv) ab = ab + h * gvel[q];
+  abar[q] = ab;
 }
 
-__global__ __launch_bounds__(kThreads) void adj_combine_kernel(
+__global__ __launch_bounds__(kBodyThreads) void adj_combine_kernel(
     int n, int sj, const double *__restrict__ part, size_t stride, double G,
     double dt, double h, double *__restrict__ gpos, double *__restrict__ gvel,
     double *__restrict__ gmass, double *__restrict__ abar, int mode) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-  gmass[i] = gmass[i] + G * split_sum(part, stride, sj, size_t(3) * n + i);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const size_t q = size_t(c) * n + i;
-    const double gx = gpos[q] + G * split_sum(part, stride, sj, q);
-    gpos[q] = gx;
-    if (mode != kAdjFinal) {
-      const double gv = gvel[q] + dt * gx;
-      gvel[q] = gv;
-      double ab = h * gv;
-      if (mode == kAdjMid) ab = ab + h * gv;
-      abar[q] = ab;
-    }
+  const size_t q = size_t(blockIdx.x) * kBodyThreads + threadIdx.x;
+  if (q >= size_t(4) * n) return;
+  const double d = G * split_sum(part, stride, sj, q);
+  if (q >= size_t(3) * n) {
+    const size_t i = q - size_t(3) * n;
+    gmass[i] = gmass[i] + d;
+    return;
+  }
+  const double gx = gpos[q] + d;
+  gpos[q] = gx;
+  if (mode != kAdjFinal) {
+    const double gv = gvel[q] + dt * gx;
+    gvel[q] = gv;
+    double ab = h * gv;
+    if (mode == kAdjMid) ab = ab + h * gv;
+    abar[q] = ab;
   }
 }
 
-inline dim3 grid1(int n) { return dim3((n + kThreads - 1) / kThreads); }
+inline dim3 grid_body(int n, int ncomp) {
+  return dim3(unsigned((size_t(ncomp) * n + kBodyThreads - 1) / kBodyThreads));
+}
+
+#define NBODY_RL_SWITCH(R_, L_, CALL)                                        \
+  do {                                                                      \
+    if (R_ == 1 && L_ == 1) { CALL(1, 1); }                                 \
+    else if (R_ == 1 && L_ == 4) { CALL(1, 4); }                            \
+    else if (R_ == 1 && L_ == 16) { CALL(1, 16); }                          \
+    else if (R_ == 2 && L_ == 1) { CALL(2, 1); }                            \
+    else if (R_ == 2 && L_ == 4) { CALL(2, 4); }                            \
+    else if (R_ == 2 && L_ == 16) { CALL(2, 16); }                          \
+    else return hipErrorInvalidValue;                                       \
+  } while (0)
 
 template <int PREC>
 hipError_t launch_accel_p(const Plan &pl, int n, const double *pos,
@@ -422,22 +493,11 @@ hipError_t launch_accel_p(const Plan &pl, int n, const double *pos,
                           double *out, size_t stride, hipStream_t st) {
   const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
   const int jc = int(pl.jchunk);
-  switch (pl.R) {
-    case 1:
-      accel_kernel<PREC, 1><<<grid, kThreads, 0, st>>>(n, pos, mass, eps2,
-                                                       scale, jc, out, stride);
-      break;
-    case 2:
-      accel_kernel<PREC, 2><<<grid, kThreads, 0, st>>>(n, pos, mass, eps2,
-                                                       scale, jc, out, stride);
-      break;
-    case 4:
-      accel_kernel<PREC, 4><<<grid, kThreads, 0, st>>>(n, pos, mass, eps2,
-                                                       scale, jc, out, stride);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
+#define NBODY_ACCEL_CALL(R_, L_)                                              \
+  accel_kernel<PREC, R_, L_><<<grid, kThreads, 0, st>>>(n, pos, mass, eps2,  \
+                                                        scale, jc, out, stride)
+  NBODY_RL_SWITCH(pl.R, pl.L, NBODY_ACCEL_CALL);
+#undef NBODY_ACCEL_CALL
   return hipGetLastError();
 }
 
@@ -448,45 +508,44 @@ hipError_t launch_vjp_p(const Plan &pl, int n, const double *pos,
                         hipStream_t st) {
   const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
   const int jc = int(pl.jchunk);
-  switch (pl.R) {
-    case 1:
-      vjp_kernel<PREC, 1><<<grid, kThreads, 0, st>>>(n, pos, mass, gacc, eps2,
-                                                     scale, jc, ox, om, stride);
-      break;
-    case 2:
-      vjp_kernel<PREC, 2><<<grid, kThreads, 0, st>>>(n, pos, mass, gacc, eps2,
-                                                     scale, jc, ox, om, stride);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
+#define NBODY_VJP_CALL(R_, L_)                                               \
+  vjp_kernel<PREC, R_, L_><<<grid, kThreads, 0, st>>>(n, pos, mass, gacc,    \
+                                                      eps2, scale, jc, ox,   \
+                                                      om, stride)
+  NBODY_RL_SWITCH(pl.R, pl.L, NBODY_VJP_CALL);
+#undef NBODY_VJP_CALL
   return hipGetLastError();
 }
+
+#undef NBODY_RL_SWITCH
 
 }  // namespace
 
 // ------------------------------------------------------------ launch plans --
 
 Plan make_plan(KernelKind kind, int precision, int64_t n) {
-  // Target bodies per thread: enough independent pair chains to hide the
-  // latency of the reciprocal square root and the LDS broadcasts, at a
-  // register cost that keeps several waves per SIMD resident.
-  int R;
-  if (kind == kAccel) R = (precision == NBODY_FP64) ? 2 : 2;
-  else R = (precision == NBODY_FP64) ? 1 : 2;
-  // Small systems: fewer bodies per thread so more waves exist at all.
-  while (R > 1 && (n + int64_t(kThreads) * R - 1) / (int64_t(kThreads) * R) < 64)
-    R /= 2;
-  Plan p;
-  p.R = R;
-  p.n_ib = (n + int64_t(kThreads) * R - 1) / (int64_t(kThreads) * R);
+  // Chosen from launch-shape sweeps on MI355X (all-pairs kernel plus split
+  // reduction).  Targets per lane R: 2 for FP64, 1 for the FP32-pair modes
+  // (their pair chain is latency-bound, so more resident waves beat more
+  // independent chains per lane).  About 8192 workgroups (32 per CU: 8
+  // resident waves per SIMD, several rounds of them), reached with the
+  // smallest lanes-per-target L in {1, 4, 16} that needs at most 64 source
+  // splits, each at least one 256-body tile long.
+  (void)kind;
+  const int R = (precision == NBODY_FP64) ? 2 : 1;
+  const int64_t target = 8192, max_sj = 64;
   const int64_t ntiles = (n + kThreads - 1) / kThreads;
-  // Split the source range until about 1024 workgroups (4 per CU) exist.
-  const int64_t target = 1024;
-  int64_t sj = (target + p.n_ib - 1) / p.n_ib;
-  if (sj < 1) sj = 1;
-  if (sj > ntiles) sj = ntiles;
-  const int64_t tiles_per_split = (ntiles + sj - 1) / sj;
+  Plan p{};
+  for (int L : {1, 4, 16}) {
+    const int64_t per_block = int64_t(kThreads / L) * R;
+    p.R = R;
+    p.L = L;
+    p.n_ib = (n + per_block - 1) / per_block;
+    p.sj = (target + p.n_ib - 1) / p.n_ib;
+    if (p.sj <= std::min(max_sj, ntiles)) break;
+  }
+  p.sj = std::max<int64_t>(1, std::min(p.sj, ntiles));
+  const int64_t tiles_per_split = (ntiles + p.sj - 1) / p.sj;
   p.jchunk = tiles_per_split * kThreads;
   p.sj = (n + p.jchunk - 1) / p.jchunk;
   return p;
@@ -530,8 +589,9 @@ hipError_t launch_vjp(const Plan &pl, int precision, int n, const double *pos,
 hipError_t launch_reduce(int n, int sj, const double *part, size_t stride,
                          double G, double *out_x, double *out_m,
                          hipStream_t st) {
-  reduce_kernel<<<grid1(n), kThreads, 0, st>>>(n, sj, part, stride, G, out_x,
-                                               out_m);
+  const int ncomp = out_m ? 4 : 3;
+  reduce_kernel<<<grid_body(n, ncomp), kBodyThreads, 0, st>>>(
+      n, ncomp, sj, part, stride, G, out_x, out_m);
   return hipGetLastError();
 }
 
@@ -540,17 +600,17 @@ hipError_t launch_update(int n, int sj, const double *part, size_t stride,
                          const double *x_in, double *x_out, const double *v_in,
                          double *v_out, double h, double dt, double *rec,
                          unsigned flags, hipStream_t st) {
-  update_kernel<<<grid1(n), kThreads, 0, st>>>(n, sj, part, stride, G, a_in,
-                                               acc_out, x_in, x_out, v_in,
-                                               v_out, h, dt, rec, flags);
+  update_kernel<<<grid_body(n, 3), kBodyThreads, 0, st>>>(
+      n, sj, part, stride, G, a_in, acc_out, x_in, x_out, v_in, v_out, h, dt,
+      rec, flags);
   return hipGetLastError();
 }
 
 hipError_t launch_adj_init(int n, const double *gvel, const double *gacc_T,
                            double h, int add_hv, double *abar, double *gmass,
                            hipStream_t st) {
-  adj_init_kernel<<<grid1(n), kThreads, 0, st>>>(n, gvel, gacc_T, h, add_hv,
-                                                 abar, gmass);
+  adj_init_kernel<<<grid_body(n, 4), kBodyThreads, 0, st>>>(
+      n, gvel, gacc_T, h, add_hv, abar, gmass);
   return hipGetLastError();
 }
 
@@ -558,7 +618,7 @@ hipError_t launch_adj_combine(int n, int sj, const double *part, size_t stride,
                               double G, double dt, double h, double *gpos,
                               double *gvel, double *gmass, double *abar,
                               int mode, hipStream_t st) {
-  adj_combine_kernel<<<grid1(n), kThreads, 0, st>>>(
+  adj_combine_kernel<<<grid_body(n, 4), kBodyThreads, 0, st>>>(
       n, sj, part, stride, G, dt, h, gpos, gvel, gmass, abar, mode);
   return hipGetLastError();
 }

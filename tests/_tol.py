@@ -73,9 +73,13 @@ def vjp_bound(pos, mass, gacc, G, eps, precision, rows=None):
     and (g_j . e) s^-3/2.  A perturbation delta of e changes the first by at
     most 12 H s^-3/2 delta / sqrt(s) and the second by 4 |g_j| s^-3/2 delta;
     the pair arithmetic adds c u of each term's magnitude bound (c = 40 for
-    the 32-operation row term), plus the chunk summation as for the
-    acceleration.  The self pair adds exactly zero (e = 0, and h is formed
-    as a difference of two rounded products, so h = 0) and is left out."""
+    the 29-operation row term), plus the chunk summation as for the
+    acceleration.  The self pair (e = 0) is left out of the sums: the kernel
+    forms h = fma(m_k, g_j, -(m_j g_k)), which for j == k is the rounding
+    error delta of m_k g_k (|delta| <= u m_k |g_k|), adds y3_self * delta
+    with y3_self = eps^-3, and subtracts the same product afterwards; what
+    remains is the rounding of that one addition, at most
+    u * eps^-3 * u * m_k |g_k| per row (added below)."""
     n = mass.size
     rows = np.arange(n) if rows is None else np.asarray(rows)
     xn = np.linalg.norm(pos, axis=0)
@@ -104,7 +108,8 @@ def vjp_bound(pos, mass, gacc, G, eps, precision, rows=None):
         # self pair: e = 0 and h = 0 exactly in the kernels
         tx[np.arange(len(blk)), blk] = 0.0
         tm[np.arange(len(blk)), blk] = 0.0
-        bx[k:k + len(blk)] = abs(G) * tx.sum(axis=1)
+        self_res = u * eps ** -3 * u * mass[blk] * gn[blk]
+        bx[k:k + len(blk)] = abs(G) * (tx.sum(axis=1) + self_res)
         bm[k:k + len(blk)] = abs(G) * tm.sum(axis=1)
         k += len(blk)
     return SAFETY * bx, SAFETY * bm
