@@ -156,7 +156,59 @@ def roofline(bench, p, kind):
             "flops_per_pair": FLOPS_PER_PAIR[kind]}
 
 
-def cpu_baseline(bench, p, gx_gpu, gv_gpu, gm_gpu):
+def shape_legs(torch, B, inputs):
+    """Kernel-level throughput at the two large target shapes: the mixed
+    forward at N = 65536 (Plummer, a = 1, eps = 1e-2) and the forward and VJP
+    at N = 262144 (clustered Plummer, a = 0.1, eps = 1e-3), each timed with
+    HIP events over back-to-back calls (kernel + split reduce)."""
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa
+    out = {}
+    for name, precs, kinds in (("plummer65536", ("mixed", "mixed_d64", "fp64"), ("accel",)),
+                               ("plummer262144_vjp", ("mixed", "mixed_d64", "fp64"),
+                                ("accel", "vjp"))):
+        w = inputs.WORKLOADS[name]
+        pos, _, mass = w.initial_state()
+        P, M = T(pos), T(mass)
+        Gt = T(inputs.upstream_normal(w.n, w.seed + 400))
+        A, GX, GM = torch.empty_like(P), torch.empty_like(P), torch.empty_like(M)
+        res = {}
+        for p in precs:
+            ws = torch.empty(max(B.nbody_workspace_bytes(B.NBODY_OP_ACCEL, w.n, 0, 1, p),
+                                 B.nbody_workspace_bytes(B.NBODY_OP_VJP, w.n, 0, 1, p), 256),
+                             dtype=torch.uint8, device=dev)
+            for kind in kinds:
+                if kind == "accel":
+                    fn = lambda: B.nbody_accel(P, M, w.G, w.eps, p, out=A, workspace=ws)  # noqa
+                else:
+                    fn = lambda: B.nbody_accel_vjp(P, M, Gt, w.G, w.eps, p, gpos=GX,  # noqa
+                                                   gmass=GM, workspace=ws)
+                reps = 20 if w.n <= 65536 else 4
+                for _ in range(2):
+                    fn()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                ips = float(w.n) * w.n / (ms * 1e-3)
+                peak = PEAK_FP64_TFLOPS if p == "fp64" else PEAK_FP32_TFLOPS
+                res["%s_%s" % (kind, p)] = {
+                    "ms": round(ms, 4), "G_int_s": round(ips / 1e9, 1),
+                    "TFLOP_s": round(ips * FLOPS_PER_PAIR[kind] / 1e12, 2),
+                    "frac_of_vector_peak": round(ips * FLOPS_PER_PAIR[kind] / 1e12 / peak, 4)}
+        if "vjp_mixed" in res:
+            for p in precs:
+                res["vjp_over_fwd_%s" % p] = round(res["vjp_%s" % p]["ms"] /
+                                                   res["accel_%s" % p]["ms"], 3)
+        out[name] = res
+    return out
+
+
+def cpu_baseline(bench, p, gx_gpu, gv_gpu, gm_gpu, x_end, v_end):
     """The FP64 oracle on the host cores over the same workload (forward plus
     exact reverse sweep), and the stated errors of the GPU results."""
     import numpy as np
@@ -182,6 +234,10 @@ def cpu_baseline(bench, p, gx_gpu, gv_gpu, gm_gpu):
     err = {"grad_vs_oracle_normwise_%s" % p: {
         "dL/dx0": metrics.normwise(gx_gpu, rx), "dL/dv0": metrics.normwise(gv_gpu, rv),
         "dL/dm": metrics.normwise(gm_gpu, rm)}}
+    # energy drift of this run's forward rollout (FP64 oracle energy)
+    e0 = sum(oracle.energy(pos, vel, mass, w.G, w.eps))
+    e1 = sum(oracle.energy(x_end, v_end, mass, w.G, w.eps))
+    err["energy_drift_%s_%dsteps" % (p, w.steps)] = float("%.3e" % (abs(e1 - e0) / abs(e0)))
     rows = w.rows(2048)
     ref = oracle.accel_rows(pos, mass, w.G, w.eps, rows)
     for q in ("fp64", "mixed", "mixed_d64"):
@@ -201,6 +257,8 @@ def main(argv=None):
     ap.add_argument("--no-legs", action="store_true",
                     help="time only the main precision's forward + adjoint")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-shapes", action="store_true",
+                    help="skip the kernel legs at N = 65536 and 262144")
     ap.add_argument("--profile", choices=["accel", "vjp"], default=None,
                     help="counter-collection mode: a 64 MiB device copy (the "
                          "traffic calibration) then --steps launches of one "
@@ -253,6 +311,7 @@ def main(argv=None):
         % (ms, wall_ms, value))
     gx, gv, gm = (bench.GX.cpu().numpy(), bench.GV.cpu().numpy(),
                   bench.GM.cpu().numpy())
+    x_end, v_end = bench.P.cpu().numpy(), bench.V.cpu().numpy()
 
     legs = {}
     if not args.no_legs:
@@ -285,10 +344,15 @@ def main(argv=None):
                                      w.G, p),
                       "n": w.n, "sim_steps": w.steps, "ckpt_every": CKPT_EVERY,
                       "precision": p, "parallelism": "single GPU"},
-           "roofline": roof, "roofline_forward": roof_fwd, "legs": legs}
+           "roofline": roof, "roofline_forward": roof_fwd, "legs": legs,
+           "vjp_over_fwd_kernel": round(roof["avg_launch_ms"] / roof_fwd["avg_launch_ms"], 3)}
+    if not args.no_shapes:
+        log("bench: kernel legs at N = 65536 and 262144")
+        out["shapes"] = shape_legs(torch, B, inputs)
+        log("bench: shapes %s" % out["shapes"])
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (FP64 oracle on the host cores)")
-        base, err = cpu_baseline(bench, p, gx, gv, gm)
+        base, err = cpu_baseline(bench, p, gx, gv, gm, x_end, v_end)
         out["cpu_baseline"] = base
         out["error"] = err
     else:
