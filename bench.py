@@ -59,6 +59,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def warm(torch, fn, seconds=0.1):
+    """Run fn untimed for about `seconds` so the GPU clock has ramped up
+    (after host-side work the first launches run up to ~12 % slower)."""
+    t0 = time.perf_counter()
+    while True:
+        fn()
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= seconds:
+            return
+
+
 class Bench:
     def __init__(self, torch, B, inputs, w):
         self.torch, self.B, self.w = torch, B, w
@@ -136,6 +147,7 @@ def roofline(bench, p, kind):
     else:
         fn = lambda: B.nbody_accel_vjp(bench.P0, bench.M, bench.GX0, w.G, w.eps, p,  # noqa
                                        gpos=bench.GX, gmass=bench.GM)
+    warm(bench.torch, fn)
     ms, _ = bench.timed(fn, reps=50, warmup=3)
     flops = FLOPS_PER_PAIR[kind] * n * n
     traffic = None
@@ -184,9 +196,7 @@ def shape_legs(torch, B, inputs):
                     fn = lambda: B.nbody_accel_vjp(P, M, Gt, w.G, w.eps, p, gpos=GX,  # noqa
                                                    gmass=GM, workspace=ws)
                 reps = 20 if w.n <= 65536 else 4
-                for _ in range(2):
-                    fn()
-                torch.cuda.synchronize()
+                warm(torch, fn)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
                 for _ in range(reps):
@@ -251,7 +261,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="timed steps")
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--precision", default="mixed",
                     choices=["fp64", "mixed", "mixed_d64"])
     ap.add_argument("--no-legs", action="store_true",
@@ -316,6 +326,7 @@ def main(argv=None):
     legs = {}
     if not args.no_legs:
         for q in ("fp64", "mixed", "mixed_d64"):
+            warm(torch, lambda: bench.forward(q))
             fms, _ = bench.timed(lambda: bench.forward(q), 10, 2)
             sms, _ = bench.timed(lambda: bench.step(q), 5, 1)
             legs[q] = {"fwd_G_int_s": round(n2s / (fms * 1e-3) / 1e9, 1),
