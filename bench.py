@@ -218,6 +218,55 @@ def shape_legs(torch, B, inputs):
     return out
 
 
+def small_rollout_leg(torch, B, inputs):
+    """The launch-bound configuration: N = 1024, 100 FP64 KDK steps (two
+    launches per step).  Timed eagerly and as a replayed HIP graph of the same
+    nbody_step call (state restored by device copies before each run)."""
+    dev = torch.device("cuda:0")
+    w = inputs.WORKLOADS["cube1024_fp64"]
+    T = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa
+    pos, vel, mass = w.initial_state()
+    P0, V0, M = T(pos), T(vel), T(mass)
+    A0 = B.nbody_accel(P0, M, w.G, w.eps, "fp64")
+    P, V, A = torch.empty_like(P0), torch.empty_like(P0), torch.empty_like(P0)
+    ws = torch.empty(max(B.nbody_workspace_bytes(B.NBODY_OP_STEP, w.n, w.steps, 1, "fp64"),
+                         256), dtype=torch.uint8, device=dev)
+
+    def run():
+        P.copy_(P0)
+        V.copy_(V0)
+        A.copy_(A0)
+        B.nbody_step(P, V, A, M, w.G, w.eps, w.dt, w.steps, "fp64", acc_valid=True,
+                     workspace=ws)
+
+    def timed(fn, reps=20):
+        warm(torch, fn)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    eager = timed(run)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    graph = timed(g.replay)
+    pairs = float(w.n) * w.n * w.steps
+    return {"workload": "%s: N=%d, %d FP64 KDK steps" % (w.name, w.n, w.steps),
+            "eager_ms": round(eager, 4), "graph_ms": round(graph, 4),
+            "eager_G_int_s": round(pairs / (eager * 1e-3) / 1e9, 1),
+            "graph_G_int_s": round(pairs / (graph * 1e-3) / 1e9, 1)}
+
+
 def cpu_baseline(bench, p, gx_gpu, gv_gpu, gm_gpu, x_end, v_end):
     """The FP64 oracle on the host cores over the same workload (forward plus
     exact reverse sweep), and the stated errors of the GPU results."""
@@ -360,6 +409,7 @@ def main(argv=None):
     if not args.no_shapes:
         log("bench: kernel legs at N = 65536 and 262144")
         out["shapes"] = shape_legs(torch, B, inputs)
+        out["shapes"]["cube1024_fp64_rollout"] = small_rollout_leg(torch, B, inputs)
         log("bench: shapes %s" % out["shapes"])
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (FP64 oracle on the host cores)")

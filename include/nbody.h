@@ -86,6 +86,13 @@ enum nbody_status {
  * bitwise identical to nbody_step(a + b steps). */
 #define NBODY_ACC_VALID 1u
 
+/* nbody_step / nbody_step_adjoint flag: integrate with the update the
+ * paper's listings print (sections 3.1-3.3) instead of kick-drift-kick: one
+ * half-kick and one drift per step with the force of the step's start,
+ *     v += (dt/2) a;  x += dt v;  a = A(x)
+ * (no closing half-kick; it is symplectic Euler for half the force). */
+#define NBODY_HALF_KICK_DRIFT 2u
+
 /* Operation selector for nbody_workspace_bytes. */
 enum nbody_op {
   NBODY_OP_ACCEL = 0,
@@ -135,7 +142,7 @@ int nbody_accel(int64_t n, const double *pos, const double *mass, double *acc,
  *                        ignored and computed first); out: A(x_steps)
  *  mass [scalar] in
  *  p    host     in      G, eps as nbody_accel; dt finite
- *  flags                 0 or NBODY_ACC_VALID
+ *  flags                 0, NBODY_ACC_VALID, NBODY_HALF_KICK_DRIFT or both
  *  ckpt device   out     nullable.  If given, ckpt_every >= 1 and it must
  *                        hold nbody_checkpoint_bytes(n, steps, ckpt_every)
  *                        bytes; record c receives (x, v, a) at step
@@ -170,12 +177,13 @@ int nbody_accel_vjp(int64_t n, const double *pos, const double *mass,
 /* Reverse sweep of nbody_step (called without NBODY_ACC_VALID, or with a
  * valid acc = A(x_0)): gradients of L(x_S, v_S, a_S) with respect to x_0,
  * v_0 and the masses.  Uses the checkpoints nbody_step wrote with the same
- * n, steps, ckpt_every, p and precision; each segment of ckpt_every steps is
- * recomputed from its checkpoint with the forward's own kernels (bitwise the
- * same trajectory), then walked backwards:
+ * n, steps, ckpt_every, p, precision and integrator flag; each segment of
+ * ckpt_every steps is recomputed from its checkpoint with the forward's own
+ * kernels (bitwise the same trajectory), then walked backwards:
  *     abar += (dt/2) vbar;  (xbar, mbar) += VJP(x_{t+1}; abar);
  *     vbar += dt xbar;      abar = (dt/2) vbar
- * ending with (xbar, mbar) += VJP(x_0; abar).
+ * ending with (xbar, mbar) += VJP(x_0; abar).  With NBODY_HALF_KICK_DRIFT
+ * the first update is absent (no closing half-kick).
  *  ckpt  device in     checkpoint buffer from nbody_step
  *  mass  [scalar] in
  *  gpos  [vector] in/out  in: dL/dx_S   out: dL/dx_0
@@ -184,14 +192,15 @@ int nbody_accel_vjp(int64_t n, const double *pos, const double *mass,
  *  gmass [scalar] out     dL/dm (overwritten)
  *  ws             >= nbody_workspace_bytes(NBODY_OP_STEP_ADJOINT, n, steps,
  *                    ckpt_every, precision)
+ *  flags          0 or NBODY_HALF_KICK_DRIFT (as given to nbody_step)
  * steps == 0 gives gpos += VJP_x(x_0; gacc_T), gmass = VJP_m(x_0; gacc_T)
  * (gvel unchanged), reading x_0 from checkpoint record 0.
  * Errors: as nbody_step; ckpt_every must be >= 1. */
 int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
                        const double *ckpt, const double *mass,
-                       const nbody_params *p, int precision, double *gpos,
-                       double *gvel, const double *gacc_T, double *gmass,
-                       void *ws, size_t ws_bytes, void *stream);
+                       const nbody_params *p, int precision, unsigned flags,
+                       double *gpos, double *gvel, const double *gacc_T,
+                       double *gmass, void *ws, size_t ws_bytes, void *stream);
 
 /* Static description of a status code (never NULL). */
 const char *nbody_error_string(int code);

@@ -53,14 +53,14 @@ def _load():
     lib.oracle_accel.argtypes = [i64, ptr, ptr, dbl, dbl, ptr]
     lib.oracle_accel_rows.argtypes = [i64, ptr, ptr, dbl, dbl, i64, ptr, ptr]
     lib.oracle_step.argtypes = [i64, i64, ptr, ptr, ptr, ptr, dbl, dbl, dbl,
-                                ctypes.c_int]
+                                ctypes.c_int, ctypes.c_int]
     lib.oracle_energy.argtypes = [i64, ptr, ptr, ptr, dbl, dbl, ptr]
     lib.oracle_momentum.argtypes = [i64, ptr, ptr, ptr]
     lib.oracle_accel_vjp.argtypes = [i64, ptr, ptr, ptr, dbl, dbl, ptr, ptr]
     lib.oracle_accel_vjp_rows.argtypes = [i64, ptr, ptr, ptr, dbl, dbl, i64,
                                           ptr, ptr, ptr]
     lib.oracle_step_adjoint.argtypes = [i64, i64, ptr, ptr, ptr, dbl, dbl, dbl,
-                                        ptr, ptr, ptr, ptr]
+                                        ctypes.c_int, ptr, ptr, ptr, ptr]
     lib.oracle_step_adjoint.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -111,8 +111,14 @@ def accel_rows(pos, mass, G, eps, rows):
     return out
 
 
-def step(pos, vel, mass, G, eps, dt, steps, acc=None):
-    """KDK leapfrog; returns (pos, vel, acc) after `steps` steps (copies)."""
+SCHEMES = {"kdk": 0, "half_kick_drift": 1}
+
+
+def step(pos, vel, mass, G, eps, dt, steps, acc=None, scheme="kdk"):
+    """Time integration; returns (pos, vel, acc) after `steps` steps (copies).
+
+    scheme "kdk": kick-drift-kick leapfrog; "half_kick_drift": the update of
+    the paper's listings (v += a dt/2; x += v dt per step)."""
     n = mass.shape[0]
     x = _vec(pos, n).copy()
     v = _vec(vel, n).copy()
@@ -122,7 +128,7 @@ def step(pos, vel, mass, G, eps, dt, steps, acc=None):
     else:
         a, valid = _vec(acc, n).copy(), 1
     _load().oracle_step(n, int(steps), _p(x), _p(v), _p(a), _p(mass), G, eps,
-                        dt, valid)
+                        dt, valid, SCHEMES[scheme])
     return x, v, a
 
 
@@ -166,7 +172,7 @@ def accel_vjp_rows(pos, mass, gacc, G, eps, rows):
 
 
 def step_adjoint(pos0, vel0, mass, G, eps, dt, steps, gpos_T, gvel_T,
-                 gacc_T=None):
+                 gacc_T=None, scheme="kdk"):
     """Exact reverse sweep of `step` from (pos0, vel0) (acc recomputed).
 
     Returns (dL/dx_0, dL/dv_0, dL/dm) for upstream (dL/dx_S, dL/dv_S[, dL/da_S]).
@@ -178,7 +184,7 @@ def step_adjoint(pos0, vel0, mass, G, eps, dt, steps, gpos_T, gvel_T,
     ga = None if gacc_T is None else _vec(gacc_T, n)
     gm = np.empty(n)
     rc = _load().oracle_step_adjoint(n, int(steps), _p(x0), _p(v0), _p(mass),
-                                     G, eps, dt, _p(gx), _p(gv),
+                                     G, eps, dt, SCHEMES[scheme], _p(gx), _p(gv),
                                      None if ga is None else _p(ga), _p(gm))
     if rc != 0:
         raise MemoryError("oracle_step_adjoint: allocation failed")

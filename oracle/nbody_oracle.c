@@ -27,8 +27,9 @@
  *  - the paper forms the force G m_i m_j d s^-3/2 and divides by m_i; the
  *    acceleration is computed here directly as G sum_j m_j d s^-3/2, which is
  *    the same quantity in exact arithmetic;
- *  - the integrator is kick-drift-kick leapfrog (the paper's listings do one
- *    half-kick and one drift per step; the workload definition asks for KDK).
+ *  - the integrator is kick-drift-kick leapfrog (scheme 0); the update the
+ *    paper's listings print -- one half-kick and one drift per step -- is
+ *    scheme 1.
  *
  * Parity pins: tests/test_oracle_pins.py checks every function here against
  * closed forms, a 40-digit decimal brute force, an independent NumPy
@@ -99,15 +100,19 @@ void oracle_accel_rows(int64_t n, const double *x, const double *m, double G,
   }
 }
 
-/* Kick-drift-kick leapfrog, `steps` steps, state updated in place.
- *   v <- v + (dt/2) a ;  x <- x + dt v ;  a <- A(x) ;  v <- v + (dt/2) a
+/* Time integration, `steps` steps, state updated in place.
+ *  scheme 0, kick-drift-kick leapfrog:
+ *    v <- v + (dt/2) a ;  x <- x + dt v ;  a <- A(x) ;  v <- v + (dt/2) a
+ *  scheme 1, the update printed in the paper's listings (sections 3.1-3.3):
+ *    one half-kick and one drift per step with the force of the step's start,
+ *    v <- v + (dt/2) a ;  x <- x + dt v ;  a <- A(x)
  * If acc_valid is 0, acc is first set to A(x).  On return acc = A(x_final).
  * The per-step data dependencies (no body moves before every force is
  * summed; no body starts step t+1 before step t ends) are those stated with
  * the pseudo-code of section 2.3. */
 void oracle_step(int64_t n, int64_t steps, double *x, double *v, double *acc,
                  const double *m, double G, double eps, double dt,
-                 int acc_valid) {
+                 int acc_valid, int scheme) {
   const double half = 0.5 * dt;
   if (!acc_valid) oracle_accel(n, x, m, G, eps, acc);
   for (int64_t t = 0; t < steps; ++t) {
@@ -116,7 +121,8 @@ void oracle_step(int64_t n, int64_t steps, double *x, double *v, double *acc,
       x[q] = x[q] + dt * v[q];
     }
     oracle_accel(n, x, m, G, eps, acc);
-    for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + half * acc[q];
+    if (scheme == 0)
+      for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + half * acc[q];
   }
 }
 
@@ -124,17 +130,11 @@ void oracle_step(int64_t n, int64_t steps, double *x, double *v, double *acc,
  * traj[(steps+1)*3*n] (used by the reverse sweep). */
 static void step_record(int64_t n, int64_t steps, double *x, double *v,
                         double *acc, const double *m, double G, double eps,
-                        double dt, double *traj) {
-  const double half = 0.5 * dt;
+                        double dt, int scheme, double *traj) {
   memcpy(traj, x, (size_t)(3 * n) * sizeof(double));
   oracle_accel(n, x, m, G, eps, acc);
   for (int64_t t = 0; t < steps; ++t) {
-    for (int64_t q = 0; q < 3 * n; ++q) {
-      v[q] = v[q] + half * acc[q];
-      x[q] = x[q] + dt * v[q];
-    }
-    oracle_accel(n, x, m, G, eps, acc);
-    for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + half * acc[q];
+    oracle_step(n, 1, x, v, acc, m, G, eps, dt, 1, scheme);
     memcpy(traj + (size_t)(t + 1) * 3 * n, x, (size_t)(3 * n) * sizeof(double));
   }
 }
@@ -243,22 +243,24 @@ void oracle_accel_vjp_rows(int64_t n, const double *x, const double *m,
   }
 }
 
-/* Reverse sweep of the kick-drift-kick loop (the exact adjoint of
- * oracle_step with acc_valid = 0).  It stores every position x_0..x_S (no
- * checkpointing) and walks the steps backwards:
+/* Reverse sweep of the integrator (the exact adjoint of oracle_step with
+ * acc_valid = 0).  It stores every position x_0..x_S (no checkpointing) and
+ * walks the steps backwards.  For kick-drift-kick (scheme 0):
  *   abar += (dt/2) vbar                  v_{t+1} = v_{t+1/2} + dt/2 a_{t+1}
  *   (xbar, mbar) += VJP(x_{t+1}; abar)   a_{t+1} = A(x_{t+1}); abar = 0
  *   vbar += dt xbar                      x_{t+1} = x_t + dt v_{t+1/2}
  *   abar  = (dt/2) vbar                  v_{t+1/2} = v_t + dt/2 a_t
- * and finishes with (xbar, mbar) += VJP(x_0; abar) for a_0 = A(x_0).
+ * and for the paper's half-kick + drift (scheme 1) the same without the
+ * first line (there is no closing half-kick).  It finishes with
+ * (xbar, mbar) += VJP(x_0; abar) for a_0 = A(x_0).
  *
  * Inputs: initial state x0, v0; gx, gv hold dL/dx_S, dL/dv_S on entry and
  * dL/dx_0, dL/dv_0 on return; ga_T (nullable) is dL/da_S; gm receives dL/dm.
  * Returns 0, or -1 if memory could not be allocated. */
 int oracle_step_adjoint(int64_t n, int64_t steps, const double *x0,
                         const double *v0, const double *m, double G,
-                        double eps, double dt, double *gx, double *gv,
-                        const double *ga_T, double *gm) {
+                        double eps, double dt, int scheme, double *gx,
+                        double *gv, const double *ga_T, double *gm) {
   const size_t q3 = (size_t)(3 * n);
   double *traj = (double *)malloc((size_t)(steps + 1) * q3 * sizeof(double));
   double *x = (double *)malloc(q3 * sizeof(double));
@@ -273,14 +275,15 @@ int oracle_step_adjoint(int64_t n, int64_t steps, const double *x0,
   }
   memcpy(x, x0, q3 * sizeof(double));
   memcpy(v, v0, q3 * sizeof(double));
-  step_record(n, steps, x, v, a, m, G, eps, dt, traj);
+  step_record(n, steps, x, v, a, m, G, eps, dt, scheme, traj);
 
   const double half = 0.5 * dt;
   for (size_t q = 0; q < q3; ++q) ab[q] = ga_T ? ga_T[q] : 0.0;
   for (int64_t i = 0; i < n; ++i) gm[i] = 0.0;
 
   for (int64_t t = steps - 1; t >= 0; --t) {
-    for (size_t q = 0; q < q3; ++q) ab[q] = ab[q] + half * gv[q];
+    if (scheme == 0)
+      for (size_t q = 0; q < q3; ++q) ab[q] = ab[q] + half * gv[q];
     oracle_accel_vjp(n, traj + (size_t)(t + 1) * q3, m, ab, G, eps, dx, dm);
     for (size_t q = 0; q < q3; ++q) gx[q] = gx[q] + dx[q];
     for (int64_t i = 0; i < n; ++i) gm[i] = gm[i] + dm[i];

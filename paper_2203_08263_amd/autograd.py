@@ -1,8 +1,9 @@
 """torch.autograd wrappers over the C ABI (no arithmetic of their own).
 
 * ``NBodyAccel``: a = A(x, m); backward calls ``nbody_accel_vjp``.
-* ``NBodyRollout``: (x_S, v_S, a_S) from S kick-drift-kick steps of
-  (x_0, v_0, m); forward calls ``nbody_step`` with a checkpoint every K steps,
+* ``NBodyRollout``: (x_S, v_S, a_S) from S steps (kick-drift-kick, or the
+  paper's half-kick + drift) of (x_0, v_0, m); forward calls ``nbody_step``
+  with a checkpoint every K steps,
   backward calls ``nbody_step_adjoint`` (segment recomputation from the
   checkpoints, then the reverse sweep).
 
@@ -42,7 +43,8 @@ class NBodyAccel(torch.autograd.Function):
 
 class NBodyRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, pos0, vel0, mass, G, eps, dt, steps, ckpt_every, precision):
+    def forward(ctx, pos0, vel0, mass, G, eps, dt, steps, ckpt_every, precision,
+                integrator="kdk"):
         mass = mass.contiguous()
         n = mass.shape[0]
         pos = pos0.detach().clone().contiguous()
@@ -52,23 +54,24 @@ class NBodyRollout(torch.autograd.Function):
         ckpt = torch.empty(B.nbody_checkpoint_bytes(n, steps, K) // 8,
                            dtype=torch.float64, device=mass.device)
         B.nbody_step(pos, vel, acc, mass, G, eps, dt, steps, precision,
-                     acc_valid=False, ckpt=ckpt, ckpt_every=K)
+                     acc_valid=False, ckpt=ckpt, ckpt_every=K, integrator=integrator)
         ctx.save_for_backward(ckpt, mass)
-        ctx.consts = (G, eps, dt, int(steps), K, precision)
+        ctx.consts = (G, eps, dt, int(steps), K, precision, integrator)
         return pos, vel, acc
 
     @staticmethod
     def backward(ctx, gpos, gvel, gacc):
         ckpt, mass = ctx.saved_tensors
-        G, eps, dt, steps, K, precision = ctx.consts
+        G, eps, dt, steps, K, precision, integrator = ctx.consts
         n = mass.shape[0]
         ref = torch.empty((3, n), dtype=torch.float64, device=mass.device)
         gx = _zeros_like(ref, gpos).clone()
         gv = _zeros_like(ref, gvel).clone()
         ga = None if gacc is None else gacc.contiguous()
         gx, gv, gm = B.nbody_step_adjoint(ckpt, mass, gx, gv, G, eps, dt, steps,
-                                          K, precision, gacc_T=ga)
-        return gx, gv, gm, None, None, None, None, None, None
+                                          K, precision, gacc_T=ga,
+                                          integrator=integrator)
+        return gx, gv, gm, None, None, None, None, None, None, None
 
 
 def accel(pos, mass, G=1.0, eps=1e-3, precision="fp64"):
@@ -76,6 +79,6 @@ def accel(pos, mass, G=1.0, eps=1e-3, precision="fp64"):
 
 
 def rollout(pos0, vel0, mass, G=1.0, eps=1e-3, dt=1e-3, steps=1, ckpt_every=10,
-            precision="fp64"):
+            precision="fp64", integrator="kdk"):
     return NBodyRollout.apply(pos0, vel0, mass, G, eps, dt, steps, ckpt_every,
-                              B._precision(precision))
+                              B._precision(precision), integrator)

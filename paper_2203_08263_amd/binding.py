@@ -25,6 +25,8 @@ PRECISIONS = {"fp64": NBODY_FP64, "mixed": NBODY_MIXED,
 
 NBODY_OK = 0
 NBODY_ACC_VALID = 1
+NBODY_HALF_KICK_DRIFT = 2
+INTEGRATORS = {"kdk": 0, "half_kick_drift": NBODY_HALF_KICK_DRIFT}
 NBODY_OP_ACCEL, NBODY_OP_STEP, NBODY_OP_VJP, NBODY_OP_STEP_ADJOINT = 0, 1, 2, 3
 NBODY_MAX_N = 1 << 28
 
@@ -74,8 +76,8 @@ def load_library():
     lib.nbody_step.argtypes = [i64, i64, vp, vp, vp, vp, pp, ci, ctypes.c_uint,
                                vp, i64, vp, sz, vp]
     lib.nbody_accel_vjp.argtypes = [i64, vp, vp, vp, vp, vp, pp, ci, vp, sz, vp]
-    lib.nbody_step_adjoint.argtypes = [i64, i64, i64, vp, vp, pp, ci, vp, vp,
-                                       vp, vp, vp, sz, vp]
+    lib.nbody_step_adjoint.argtypes = [i64, i64, i64, vp, vp, pp, ci,
+                                       ctypes.c_uint, vp, vp, vp, vp, vp, sz, vp]
     for f in ("nbody_accel", "nbody_step", "nbody_accel_vjp",
               "nbody_step_adjoint"):
         getattr(lib, f).restype = ci
@@ -175,10 +177,17 @@ def nbody_accel(pos, mass, G=1.0, eps=1e-3, precision=NBODY_FP64, out=None,
     return acc
 
 
+def _integrator(name) -> int:
+    if name not in INTEGRATORS:
+        raise ValueError("unknown integrator %r (kdk or half_kick_drift)" % (name,))
+    return INTEGRATORS[name]
+
+
 def nbody_step(pos, vel, acc, mass, G=1.0, eps=1e-3, dt=1e-3, steps=1,
                precision=NBODY_FP64, acc_valid=False, ckpt=None, ckpt_every=0,
-               workspace=None):
-    """`steps` KDK leapfrog steps in place on pos, vel, acc."""
+               workspace=None, integrator="kdk"):
+    """`steps` time steps in place on pos, vel, acc.  integrator "kdk"
+    (kick-drift-kick leapfrog) or "half_kick_drift" (the paper's listings)."""
     lib = load_library()
     n = mass.shape[0]
     dev = mass.device
@@ -198,7 +207,7 @@ def nbody_step(pos, vel, acc, mass, G=1.0, eps=1e-3, dt=1e-3, steps=1,
     ws, wsb = _workspace(lib.nbody_workspace_bytes(NBODY_OP_STEP, n, steps, 1, prec),
                          dev, workspace)
     prm = _Params(G, eps, dt)
-    flags = NBODY_ACC_VALID if acc_valid else 0
+    flags = (NBODY_ACC_VALID if acc_valid else 0) | _integrator(integrator)
     _check(lib.nbody_step(n, int(steps), _ptr(pos), _ptr(vel), _ptr(acc),
                           _ptr(mass), ctypes.byref(prm), prec, flags, _ptr(ckpt),
                           int(ckpt_every), _ptr(ws), wsb, _stream(dev)))
@@ -230,7 +239,7 @@ def nbody_accel_vjp(pos, mass, gacc, G=1.0, eps=1e-3, precision=NBODY_FP64,
 
 def nbody_step_adjoint(ckpt, mass, gpos, gvel, G=1.0, eps=1e-3, dt=1e-3,
                        steps=1, ckpt_every=1, precision=NBODY_FP64,
-                       gacc_T=None, gmass=None, workspace=None):
+                       gacc_T=None, gmass=None, workspace=None, integrator="kdk"):
     """Reverse sweep: gpos/gvel (in: dL/dx_S, dL/dv_S) become dL/dx_0, dL/dv_0
     in place; returns (gpos, gvel, gmass)."""
     lib = load_library()
@@ -255,7 +264,8 @@ def nbody_step_adjoint(ckpt, mass, gpos, gvel, G=1.0, eps=1e-3, dt=1e-3,
                                                    ckpt_every, prec), dev, workspace)
     prm = _Params(G, eps, dt)
     _check(lib.nbody_step_adjoint(n, int(steps), int(ckpt_every), _ptr(ckpt),
-                                  _ptr(mass), ctypes.byref(prm), prec, _ptr(gpos),
+                                  _ptr(mass), ctypes.byref(prm), prec,
+                                  _integrator(integrator), _ptr(gpos),
                                   _ptr(gvel), _ptr(gacc_T), _ptr(gmass), _ptr(ws),
                                   wsb, _stream(dev)))
     return gpos, gvel, gmass

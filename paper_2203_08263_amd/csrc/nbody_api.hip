@@ -193,9 +193,9 @@ int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
   if (steps < 0)
     return fail(NBODY_ERR_INVALID_ARGUMENT, "steps = %lld < 0",
                 (long long)steps);
-  if (flags & ~NBODY_ACC_VALID)
+  if (flags & ~(NBODY_ACC_VALID | NBODY_HALF_KICK_DRIFT))
     return fail(NBODY_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x",
-                flags & ~NBODY_ACC_VALID);
+                flags & ~(NBODY_ACC_VALID | NBODY_HALF_KICK_DRIFT));
   if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(vel, "vel")) ||
       (rc = check_ptr(acc, "acc")) || (rc = check_ptr(mass, "mass")))
     return rc;
@@ -218,8 +218,10 @@ int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
   hipError_t e;
 
   // Step 0: a_0 (computed or given), checkpoint record 0, opening half-kick
-  // and drift.
+  // and drift.  The paper's update has no closing half-kick.
   const bool have_acc = flags & NBODY_ACC_VALID;
+  const unsigned close_flag =
+      (flags & NBODY_HALF_KICK_DRIFT) ? 0u : unsigned(nbody::kClose);
   if (!have_acc) {
     if ((rc = accel_to_parts(pl, precision, nn, pos, mass, eps2, part, st)))
       return rc;
@@ -238,7 +240,7 @@ int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
     double *rec = nullptr;
     if (ckpt && more && (t + 1) % ckpt_every == 0)
       rec = ckpt + size_t((t + 1) / ckpt_every) * rec_len;
-    const unsigned fl = nbody::kClose | (more ? unsigned(nbody::kOpen) : 0u);
+    const unsigned fl = close_flag | (more ? unsigned(nbody::kOpen) : 0u);
     e = nbody::launch_update(nn, int(pl.sj), part, stride, G, nullptr, acc,
                              pos, pos, vel, vel, h, dt, rec, fl, st);
     if (e != hipSuccess) return hip_fail(e, "update kernel launch");
@@ -278,11 +280,15 @@ int nbody_accel_vjp(int64_t n, const double *pos, const double *mass,
 
 int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
                        const double *ckpt, const double *mass,
-                       const nbody_params *p, int precision, double *gpos,
-                       double *gvel, const double *gacc_T, double *gmass,
-                       void *ws, size_t ws_bytes, void *stream) {
+                       const nbody_params *p, int precision, unsigned flags,
+                       double *gpos, double *gvel, const double *gacc_T,
+                       double *gmass, void *ws, size_t ws_bytes, void *stream) {
   int rc;
   if ((rc = check_common(n, p, precision, true))) return rc;
+  if (flags & ~NBODY_HALF_KICK_DRIFT)
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x",
+                flags & ~NBODY_HALF_KICK_DRIFT);
+  const bool kdk = !(flags & NBODY_HALF_KICK_DRIFT);
   if (steps < 0)
     return fail(NBODY_ERR_INVALID_ARGUMENT, "steps = %lld < 0",
                 (long long)steps);
@@ -319,7 +325,10 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
   double *part = reinterpret_cast<double *>(w);
   hipError_t e;
 
-  e = nbody::launch_adj_init(nn, gvel, gacc_T, h, steps > 0, abar, gmass, st);
+  // abar_S = dL/da_S, plus (dt/2) dL/dv_S through the closing half-kick of
+  // the last step (kick-drift-kick only).
+  e = nbody::launch_adj_init(nn, gvel, gacc_T, h, kdk && steps > 0, abar,
+                             gmass, st);
   if (e != hipSuccess) return hip_fail(e, "adjoint init launch");
 
   const int64_t nrec = num_records(steps, ckpt_every);
@@ -339,7 +348,10 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
         return rc;
       e = nbody::launch_update(nn, int(pf.sj), part, q3, G, nullptr, a_ws, xp,
                                seg + size_t(t) * q3, v_ws, v_ws, h, dt,
-                               nullptr, nbody::kClose | nbody::kOpen, st);
+                               nullptr,
+                               (kdk ? unsigned(nbody::kClose) : 0u) |
+                                   unsigned(nbody::kOpen),
+                               st);
       if (e != hipSuccess) return hip_fail(e, "update kernel launch");
     }
     // Reverse sweep over steps s0+k-1 .. s0: VJP at x_{t+1} = seg[t - s0].
@@ -348,9 +360,12 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
       e = nbody::launch_vjp(pv, precision, nn, xt1, mass, abar, eps2, 1.0,
                             part, part + q3, size_t(4) * n, st);
       if (e != hipSuccess) return hip_fail(e, "vjp kernel launch");
+      // abar_t = (dt/2) vbar from the opening half-kick of step t, plus the
+      // closing half-kick of step t-1 under kick-drift-kick.
       e = nbody::launch_adj_combine(nn, int(pv.sj), part, size_t(4) * n, G, dt,
                                     h, gpos, gvel, gmass, abar,
-                                    t > 0 ? nbody::kAdjMid : nbody::kAdjLast,
+                                    (kdk && t > 0) ? nbody::kAdjMid
+                                                   : nbody::kAdjLast,
                                     st);
       if (e != hipSuccess) return hip_fail(e, "adjoint combine launch");
     }

@@ -116,7 +116,7 @@ def vjp_bound(pos, mass, gacc, G, eps, precision, rows=None):
 
 
 def adjoint_bound(oracle, pos, vel, mass, G, eps, dt, steps, gx, gv, ga,
-                  precision, rows=None):
+                  precision, rows=None, scheme="kdk"):
     """Element-wise bounds (dL/dx_0, dL/dv_0, dL/dm) of the GPU reverse sweep.
 
     The reverse sweep is linear in the upstream gradients; its only
@@ -125,30 +125,44 @@ def adjoint_bound(oracle, pos, vel, mass, G, eps, dt, steps, gx, gv, ga,
     at most vjp_bound(x_{t+1}, abar_t) to xbar and mbar.  An xbar error
     reaches vbar through vbar += dt xbar, and abar through (dt/2) vbar, whose
     effect on later VJPs is second order in dt and covered by a 25% margin.
+    The sweep's own FP64 updates add at most 2 u64 of each running value per
+    step (the GPU fuses vbar + dt xbar into one FMA, the oracle does not).
     With `rows`, bounds are formed for those rows only (the sweep itself is
-    still exact over all bodies).
+    still exact over all bodies).  scheme "half_kick_drift" walks the sweep
+    of the paper's update (no closing half-kick).
     """
+    kdk = scheme == "kdk"
     h = 0.5 * dt
     traj = [np.array(pos, dtype=np.float64)]
     x, v, a = pos, vel, None
     for _ in range(steps):
-        x, v, a = oracle.step(x, v, mass, G, eps, dt, 1, acc=a)
+        x, v, a = oracle.step(x, v, mass, G, eps, dt, 1, acc=a, scheme=scheme)
         traj.append(x)
     gxc = np.array(gx, dtype=np.float64)
     gvc = np.array(gv, dtype=np.float64)
-    ab = (np.zeros_like(gxc) if ga is None else np.array(ga)) + (h * gvc if steps else 0)
+    ab = (np.zeros_like(gxc) if ga is None else np.array(ga)) + (
+        h * gvc if (steps and kdk) else 0)
     m = mass.size if rows is None else len(rows)
+    sel = slice(None) if rows is None else np.asarray(rows)
     Bx, Bv, Bm = np.zeros(m), np.zeros(m), np.zeros(m)
+    gmc = np.zeros(mass.size)
+
+    def nrm(v):
+        return np.sqrt((v[:, sel] ** 2).sum(axis=0))
+
     for t in range(steps - 1, -1, -1):
         vx, vm = oracle.accel_vjp(traj[t + 1], mass, ab, G, eps)
         bx, bm = vjp_bound(traj[t + 1], mass, ab, G, eps, precision, rows)
-        Bx += bx
-        Bm += bm
         gxc = gxc + vx
+        gmc = gmc + vm
         gvc = gvc + dt * gxc
-        Bv += dt * Bx
-        ab = h * gvc + (h * gvc if t > 0 else 0)
+        # the sweep's own FP64 roundings (xbar += VJP, vbar += dt xbar)
+        Bx += bx + 2 * U64 * nrm(gxc)
+        Bm += bm + 2 * U64 * np.abs(gmc[sel])
+        Bv += dt * Bx + 2 * U64 * nrm(gvc)
+        ab = h * gvc + (h * gvc if (t > 0 and kdk) else 0)
     bx, bm = vjp_bound(traj[0], mass, ab, G, eps, precision, rows)
-    Bx += bx
-    Bm += bm
+    vx, vm = oracle.accel_vjp(traj[0], mass, ab, G, eps)
+    Bx += bx + 2 * U64 * nrm(gxc + vx)
+    Bm += bm + 2 * U64 * np.abs((gmc + vm)[sel])
     return 1.25 * Bx, 1.25 * Bv, 1.25 * Bm

@@ -57,6 +57,8 @@ def test_header_enums_match_binding(B):
         m = re.search(r"\b%s\s*=\s*(\d+)" % name, txt)
         assert m and int(m.group(1)) == val
     assert "#define NBODY_ACC_VALID 1u" in txt
+    assert "#define NBODY_HALF_KICK_DRIFT 2u" in txt
+    assert B.NBODY_HALF_KICK_DRIFT == 2
     assert "#define NBODY_MAX_N ((int64_t)1 << 28)" in txt
 
 
@@ -157,7 +159,8 @@ def test_step_rejects_invalid_arguments(B):
                               _params(B, dt=dt), 0, flags, _p(ckpt), K, _p(FAKE),
                               wsb, None)
     assert step(steps=-1) == 1
-    assert step(flags=2) == 1
+    assert step(flags=4) == 1
+    assert step(flags=8 | 1) == 1
     assert step(ckpt=FAKE, K=0) == 1
     assert step(dt=math.nan) == 1
     assert step(vel=0) == 1
@@ -172,15 +175,16 @@ def test_vjp_and_adjoint_reject_invalid_arguments(B):
                                _params(B), 0, _p(FAKE), 1 << 30, None) == 1
     ws = B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, n, 10, 5, 1)
 
-    def adj(steps=10, K=5, ckpt=FAKE, gacc=None, wsb=ws, prec=1):
+    def adj(steps=10, K=5, ckpt=FAKE, gacc=None, wsb=ws, prec=1, flags=0):
         return lib.nbody_step_adjoint(n, steps, K, _p(ckpt), _p(FAKE), _params(B),
-                                      prec, _p(FAKE), _p(FAKE), _p(gacc), _p(FAKE),
-                                      _p(FAKE), wsb, None)
+                                      prec, flags, _p(FAKE), _p(FAKE), _p(gacc),
+                                      _p(FAKE), _p(FAKE), wsb, None)
     assert adj(K=0) == 1
     assert adj(steps=-2) == 1
     assert adj(ckpt=0) == 1
     assert adj(gacc=FAKE + 2) == 1
     assert adj(prec=5) == 1
+    assert adj(flags=1) == 1   # NBODY_ACC_VALID is not an adjoint flag
     assert adj(wsb=ws - 256) == 2
 
 

@@ -331,3 +331,89 @@ def test_autograd_rollout(B, dev, oracle, prec):
         _check_bound(N(P.grad), rx, bx + np.sqrt(3) * dxs, "grad x0")
         _check_bound(N(V.grad), rv, bv + np.sqrt(3) * dxs * S * 1e-3 * 2, "grad v0")
         assert np.all(np.abs(N(M.grad) - rm) <= bm + 1e-6 * np.abs(rm).max())
+
+
+# ------------------------------------- the paper's half-kick + drift update --
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_half_kick_drift_step_parity_and_chaining(B, dev, oracle, prec):
+    say("half-kick-drift step", prec)
+    n, S, dt, eps = 1000, 20, 1e-3, 1e-3
+    pos, vel, mass, P, V, M = _state(n, 61, dev)
+    A = torch.empty_like(P)
+    B.nbody_step(P, V, A, M, 1.0, eps, dt, S, prec, integrator="half_kick_drift")
+    x, v, a = oracle.step(pos, vel, mass, 1.0, eps, dt, S, scheme="half_kick_drift")
+    ex = np.linalg.norm(N(P) - x) / np.linalg.norm(x)
+    ev = np.linalg.norm(N(V) - v) / np.linalg.norm(v)
+    say("  state err x %.2e v %.2e" % (ex, ev))
+    if prec == "fp64":
+        assert ex <= 1e-12 and ev <= 1e-12
+    else:
+        ab = _tol.accel_bound(pos, mass, 1.0, eps, prec).max()
+        assert np.abs(N(V) - v).max() <= 2 * S * dt * ab
+        assert np.abs(N(P) - x).max() <= 2 * S * S * dt * dt * ab
+    # it is not kick-drift-kick, and chaining is bitwise
+    P2, V2, A2 = T(pos, dev), T(vel, dev), torch.empty_like(P)
+    B.nbody_step(P2, V2, A2, M, 1.0, eps, dt, 12, prec, integrator="half_kick_drift")
+    B.nbody_step(P2, V2, A2, M, 1.0, eps, dt, 8, prec, acc_valid=True,
+                 integrator="half_kick_drift")
+    assert torch.equal(P2, P) and torch.equal(V2, V) and torch.equal(A2, A)
+    xk, _, _ = oracle.step(pos, vel, mass, 1.0, eps, dt, S)
+    assert np.abs(xk - x).max() > 1e3 * max(np.abs(N(P) - x).max(), 1e-300)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_half_kick_drift_adjoint_vs_oracle(B, dev, oracle, prec):
+    say("half-kick-drift adjoint", prec)
+    n, S = 300, 11
+    pos, vel, mass = inputs.uniform_cube(n, 62)
+    gx = inputs.upstream_normal(n, 63)
+    gv = inputs.upstream_normal(n, 64, 0.1)
+    ga = inputs.upstream_normal(n, 65, 1e-3)
+    rx, rv, rm = oracle.step_adjoint(pos, vel, mass, 1.0, 1e-3, 1e-3, S, gx, gv, ga,
+                                     scheme="half_kick_drift")
+    outs = []
+    for K in (1, 4, 11):
+        P, V, M = T(pos, dev), T(vel, dev), T(mass, dev)
+        A = torch.empty_like(P)
+        ck = torch.empty(B.nbody_checkpoint_bytes(n, S, K) // 8, dtype=torch.float64,
+                         device=dev)
+        B.nbody_step(P, V, A, M, 1.0, 1e-3, 1e-3, S, prec, ckpt=ck, ckpt_every=K,
+                     integrator="half_kick_drift")
+        GX, GV = T(gx, dev), T(gv, dev)
+        _, _, GM = B.nbody_step_adjoint(ck, M, GX, GV, 1.0, 1e-3, 1e-3, S, K, prec,
+                                        gacc_T=T(ga, dev), integrator="half_kick_drift")
+        outs.append((N(GX), N(GV), N(GM)))
+    for o in outs[1:]:
+        for a_, b_ in zip(o, outs[0]):
+            assert np.array_equal(a_, b_)
+    ox, ov, om = outs[0]
+    errs = [np.linalg.norm(o - r) / np.linalg.norm(r)
+            for o, r in ((ox, rx), (ov, rv), (om, rm))]
+    say("  normwise err x %.2e v %.2e m %.2e" % tuple(errs))
+    if prec == "fp64":
+        assert max(errs) <= 1e-12
+    bx, bv, bm = _tol.adjoint_bound(oracle, pos, vel, mass, 1.0, 1e-3, 1e-3, S,
+                                    gx, gv, ga, prec, scheme="half_kick_drift")
+    _check_bound(ox, rx, bx, prec + " dL/dx0")
+    _check_bound(ov, rv, bv, prec + " dL/dv0")
+    assert np.all(np.abs(om - rm) <= bm), prec + " dL/dm"
+
+
+def test_half_kick_drift_autograd_rollout(B, dev, oracle):
+    say("half-kick-drift autograd")
+    from paper_2203_08263_amd import rollout
+    n, S, K = 256, 9, 4
+    pos, vel, mass = inputs.uniform_cube(n, 66)
+    tgt = inputs.uniform_cube(n, 67)[0]
+    P = T(pos, dev).requires_grad_(True)
+    V = T(vel, dev).requires_grad_(True)
+    M = T(mass, dev).requires_grad_(True)
+    xS, _, _ = rollout(P, V, M, 1.0, 1e-3, 1e-3, S, K, "fp64", integrator="half_kick_drift")
+    ((xS - T(tgt, dev)) ** 2).sum().backward()
+    x_o, _, _ = oracle.step(pos, vel, mass, 1.0, 1e-3, 1e-3, S, scheme="half_kick_drift")
+    rx, rv, rm = oracle.step_adjoint(pos, vel, mass, 1.0, 1e-3, 1e-3, S,
+                                     2 * (x_o - tgt), np.zeros((3, n)),
+                                     scheme="half_kick_drift")
+    for got, ref in ((P.grad, rx), (V.grad, rv), (M.grad, rm)):
+        assert np.linalg.norm(N(got) - ref) / np.linalg.norm(ref) <= 1e-12

@@ -410,3 +410,65 @@ def test_step_adjoint_zero_steps_is_vjp(oracle):
     vp, vm = oracle.accel_vjp(pos, mass, ga, 1.0, 1e-3)
     assert np.array_equal(ov, gv)
     assert np.array_equal(ox, gx + vp) and np.array_equal(om, vm)
+
+
+# ------------------------------------ the paper's half-kick + drift update --
+# The listings (sections 3.1-3.3) update v += a dt/2; x += v dt once per step
+# with the force of the step's start.  That is exactly symplectic Euler for
+# half the force a/2: it must converge -- at first order -- to the orbit of a
+# half-strength system, not to the true one.
+
+def test_half_kick_drift_orbit_half_force_first_order(oracle):
+    m1, m2, R, eps, G = 1.0, 0.5, 1.0, 0.3, 1.0
+    # circular orbit of the half-strength system (G/2)
+    pos, vel, mass, w, r1, r2 = _circular_two_body(m1, m2, R, eps, G / 2)
+    errs = []
+    for nsteps in (2000, 4000):
+        T = 2 * math.pi / w
+        x, v, _ = oracle.step(pos, vel, mass, G, eps, T / nsteps, nsteps,
+                              scheme="half_kick_drift")
+        errs.append(np.abs(x - pos).max())
+    assert errs[0] < 5e-2
+    assert 1.7 < errs[0] / errs[1] < 2.3
+    # and it is not the full-strength orbit
+    pos_f, vel_f, _, wf, _, _ = _circular_two_body(m1, m2, R, eps, G)
+    xf, _, _ = oracle.step(pos_f, vel_f, mass, G, eps, 2 * math.pi / wf / 2000, 2000,
+                           scheme="half_kick_drift")
+    assert np.abs(xf - pos_f).max() > 0.1
+
+
+def test_half_kick_drift_momentum_and_chaining(oracle):
+    pos, vel, mass = inputs.uniform_cube(96, 26)
+    x1, v1, a1 = oracle.step(pos, vel, mass, 1.0, 1e-3, 1e-3, 6, scheme="half_kick_drift")
+    x2, v2, a2 = oracle.step(x1, v1, mass, 1.0, 1e-3, 1e-3, 4, acc=a1,
+                             scheme="half_kick_drift")
+    x3, v3, a3 = oracle.step(pos, vel, mass, 1.0, 1e-3, 1e-3, 10, scheme="half_kick_drift")
+    assert np.array_equal(x2, x3) and np.array_equal(v2, v3) and np.array_equal(a2, a3)
+    p0, p1 = oracle.momentum(vel, mass), oracle.momentum(v3, mass)
+    assert np.all(np.abs(p1 - p0) <= 1e-14 * (mass * np.abs(vel).sum(0)).sum() * 10)
+    # differs from KDK
+    xk, _, _ = oracle.step(pos, vel, mass, 1.0, 1e-3, 1e-3, 10)
+    assert not np.array_equal(xk, x3)
+
+
+def test_half_kick_drift_adjoint_central_fd(oracle):
+    rng = _rng(47)
+    n, G, eps, dt, S = 6, 1.0, 0.2, 0.02, 7
+    pos = rng.uniform(-1, 1, (3, n))
+    vel = rng.normal(0, 0.3, (3, n))
+    mass = rng.uniform(0.5, 1.0, n)
+    cx, cv, ca = rng.normal(size=(3, n)), rng.normal(size=(3, n)), rng.normal(size=(3, n))
+
+    def loss(x0, v0, m):
+        x, v, a = oracle.step(x0, v0, m, G, eps, dt, S, scheme="half_kick_drift")
+        return float((cx * x).sum() + (cv * v).sum() + (ca * a).sum())
+
+    gx, gv, gm = oracle.step_adjoint(pos, vel, mass, G, eps, dt, S, cx, cv, ca,
+                                     scheme="half_kick_drift")
+    h = 1e-6
+    np.testing.assert_allclose(gx, _central_fd(lambda z: loss(z, vel, mass), pos, h),
+                               rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(gv, _central_fd(lambda z: loss(pos, z, mass), vel, h),
+                               rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(gm, _central_fd(lambda z: loss(pos, vel, z), mass, h),
+                               rtol=1e-6, atol=1e-7)
