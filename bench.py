@@ -43,7 +43,8 @@ PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64, published
 # square root as 2: the force pair (3 sub, 3 FMA, rsqrt, 3 mul, 3 FMA) is the
 # paper's 20; the VJP pair (3 sub, 3 FMA, rsqrt, 2 mul, 3 mul + 3 FMA for h,
 # 1 mul + 2 FMA twice for e.h and gbar.e, 1 FMA, 2 mul, 6 FMA) is 48.
-FLOPS_PER_PAIR = {"accel": 20, "vjp": 48}
+# The potential pair (diagnostics) is 3 sub, 3 FMA, rsqrt, 1 FMA = 13.
+FLOPS_PER_PAIR = {"accel": 20, "vjp": 48, "diag": 13}
 # HBM bytes per launch of the roofline kernel from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE, each scaled by what the counter reads for a
 # 64 MiB device copy; profiles/vjp_kernel_cube16384_mixed_traffic.md).  They
@@ -169,29 +170,37 @@ def roofline(bench, p, kind):
 
 
 def shape_legs(torch, B, inputs):
-    """Kernel-level throughput at the two large target shapes: the mixed
-    forward at N = 65536 (Plummer, a = 1, eps = 1e-2) and the forward and VJP
-    at N = 262144 (clustered Plummer, a = 0.1, eps = 1e-3), each timed with
-    HIP events over back-to-back calls (kernel + split reduce)."""
+    """Kernel-level throughput at the two large target shapes: the forward
+    and the energy diagnostics at N = 65536 (Plummer, a = 1, eps = 1e-2) and
+    the forward and VJP at N = 262144 (clustered Plummer, a = 0.1,
+    eps = 1e-3), each timed with HIP events over back-to-back calls (kernel +
+    split reduce)."""
     dev = torch.device("cuda:0")
     T = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa
     out = {}
-    for name, precs, kinds in (("plummer65536", ("mixed", "mixed_d64", "fp64"), ("accel",)),
+    for name, precs, kinds in (("plummer65536", ("mixed", "mixed_d64", "fp64"),
+                                ("accel", "diag")),
                                ("plummer262144_vjp", ("mixed", "mixed_d64", "fp64"),
                                 ("accel", "vjp"))):
         w = inputs.WORKLOADS[name]
-        pos, _, mass = w.initial_state()
-        P, M = T(pos), T(mass)
+        pos, vel, mass = w.initial_state()
+        P, M, Vt = T(pos), T(mass), T(vel)
+        D = torch.empty(9, dtype=torch.float64, device=dev)
         Gt = T(inputs.upstream_normal(w.n, w.seed + 400))
         A, GX, GM = torch.empty_like(P), torch.empty_like(P), torch.empty_like(M)
         res = {}
         for p in precs:
             ws = torch.empty(max(B.nbody_workspace_bytes(B.NBODY_OP_ACCEL, w.n, 0, 1, p),
-                                 B.nbody_workspace_bytes(B.NBODY_OP_VJP, w.n, 0, 1, p), 256),
+                                 B.nbody_workspace_bytes(B.NBODY_OP_VJP, w.n, 0, 1, p),
+                                 B.nbody_workspace_bytes(B.NBODY_OP_DIAGNOSTICS, w.n, 0, 1,
+                                                         p), 256),
                              dtype=torch.uint8, device=dev)
             for kind in kinds:
                 if kind == "accel":
                     fn = lambda: B.nbody_accel(P, M, w.G, w.eps, p, out=A, workspace=ws)  # noqa
+                elif kind == "diag":
+                    fn = lambda: B.nbody_diagnostics(P, Vt, M, w.G, w.eps, p, out=D,  # noqa
+                                                     workspace=ws)
                 else:
                     fn = lambda: B.nbody_accel_vjp(P, M, Gt, w.G, w.eps, p, gpos=GX,  # noqa
                                                    gmass=GM, workspace=ws)

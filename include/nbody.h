@@ -98,7 +98,8 @@ enum nbody_op {
   NBODY_OP_ACCEL = 0,
   NBODY_OP_STEP = 1,
   NBODY_OP_VJP = 2,
-  NBODY_OP_STEP_ADJOINT = 3
+  NBODY_OP_STEP_ADJOINT = 3,
+  NBODY_OP_DIAGNOSTICS = 4
 };
 
 /* Largest supported body count. */
@@ -201,6 +202,23 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
                        const nbody_params *p, int precision, unsigned flags,
                        double *gpos, double *gvel, const double *gacc_T,
                        double *gmass, void *ws, size_t ws_bytes, void *stream);
+
+/* Conserved quantities of the softened system, a diagnostic for energy
+ * drift and momentum conservation along a rollout (the energy whose negative
+ * gradient is the section 2.3 force):
+ *  out [device, 9 doubles, written]:
+ *    out[0] K = sum_i m_i |v_i|^2 / 2
+ *    out[1] W = -G sum_{i<j} m_i m_j (|x_i - x_j|^2 + eps^2)^(-1/2)
+ *    out[2..4] sum_i m_i v_i      out[5..7] sum_i m_i x_i     out[8] sum_i m_i
+ *  pos, vel [vector] in; mass [scalar] in; p: G, eps as nbody_accel
+ *  precision  pair arithmetic of W as in nbody_accel (FP32 partial sums over
+ *             chunks of 32 sources in the mixed modes); every other sum is
+ *             FP64.  All sums are taken in a fixed order (no atomics).
+ *  ws >= nbody_workspace_bytes(NBODY_OP_DIAGNOSTICS)
+ * Errors: as nbody_accel. */
+int nbody_diagnostics(int64_t n, const double *pos, const double *vel,
+                      const double *mass, const nbody_params *p, int precision,
+                      double *out, void *ws, size_t ws_bytes, void *stream);
 
 /* Static description of a status code (never NULL). */
 const char *nbody_error_string(int code);

@@ -28,11 +28,12 @@ NBODY_ACC_VALID = 1
 NBODY_HALF_KICK_DRIFT = 2
 INTEGRATORS = {"kdk": 0, "half_kick_drift": NBODY_HALF_KICK_DRIFT}
 NBODY_OP_ACCEL, NBODY_OP_STEP, NBODY_OP_VJP, NBODY_OP_STEP_ADJOINT = 0, 1, 2, 3
+NBODY_OP_DIAGNOSTICS = 4
 NBODY_MAX_N = 1 << 28
 
 SYMBOLS = ("nbody_workspace_bytes", "nbody_checkpoint_bytes", "nbody_accel",
            "nbody_step", "nbody_accel_vjp", "nbody_step_adjoint",
-           "nbody_error_string", "nbody_last_error")
+           "nbody_diagnostics", "nbody_error_string", "nbody_last_error")
 
 _INVALID = ctypes.c_size_t(-1).value
 
@@ -78,8 +79,9 @@ def load_library():
     lib.nbody_accel_vjp.argtypes = [i64, vp, vp, vp, vp, vp, pp, ci, vp, sz, vp]
     lib.nbody_step_adjoint.argtypes = [i64, i64, i64, vp, vp, pp, ci,
                                        ctypes.c_uint, vp, vp, vp, vp, vp, sz, vp]
+    lib.nbody_diagnostics.argtypes = [i64, vp, vp, vp, pp, ci, vp, vp, sz, vp]
     for f in ("nbody_accel", "nbody_step", "nbody_accel_vjp",
-              "nbody_step_adjoint"):
+              "nbody_step_adjoint", "nbody_diagnostics"):
         getattr(lib, f).restype = ci
     lib.nbody_error_string.argtypes = [ci]
     lib.nbody_error_string.restype = ctypes.c_char_p
@@ -269,3 +271,27 @@ def nbody_step_adjoint(ckpt, mass, gpos, gvel, G=1.0, eps=1e-3, dt=1e-3,
                                   _ptr(gvel), _ptr(gacc_T), _ptr(gmass), _ptr(ws),
                                   wsb, _stream(dev)))
     return gpos, gvel, gmass
+
+
+def nbody_diagnostics(pos, vel, mass, G=1.0, eps=1e-3, precision=NBODY_FP64,
+                      out=None, workspace=None):
+    """Device tensor (9,): kinetic energy, softened potential energy,
+    momentum (3), mass-weighted position sum (3), total mass."""
+    lib = load_library()
+    n = mass.shape[0]
+    dev = mass.device
+    _scal(mass, n, "mass")
+    _vec(pos, n, "pos", dev)
+    _vec(vel, n, "vel", dev)
+    prec = _precision(precision)
+    if out is None:
+        out = torch.empty(9, dtype=torch.float64, device=dev)
+    elif out.dtype != torch.float64 or out.numel() < 9 or not out.is_contiguous() \
+            or out.device != dev:
+        raise ValueError("out must be a contiguous float64 tensor of >= 9 on %s" % dev)
+    ws, wsb = _workspace(lib.nbody_workspace_bytes(NBODY_OP_DIAGNOSTICS, n, 0, 1, prec),
+                         dev, workspace)
+    prm = _Params(G, eps, 0.0)
+    _check(lib.nbody_diagnostics(n, _ptr(pos), _ptr(vel), _ptr(mass), ctypes.byref(prm),
+                                 prec, _ptr(out), _ptr(ws), wsb, _stream(dev)))
+    return out

@@ -94,6 +94,10 @@ size_t ws_vjp(int64_t n, int prec) {
   const Plan pl = nbody::make_plan(nbody::kVjp, prec, n);
   return pl.sj > 1 ? dbytes(pl.sj * 4 * n) : 0;
 }
+size_t ws_diag(int64_t n, int prec) {
+  const Plan pl = nbody::make_plan(nbody::kPotential, prec, n);
+  return dbytes(pl.sj * n) + dbytes(((n + nbody::kThreads - 1) / nbody::kThreads) * 9);
+}
 size_t ws_part_adjoint(int64_t n, int prec) {
   const Plan pf = nbody::make_plan(nbody::kAccel, prec, n);
   const Plan pv = nbody::make_plan(nbody::kVjp, prec, n);
@@ -146,6 +150,7 @@ size_t nbody_workspace_bytes(int op, int64_t n, int64_t steps,
     case NBODY_OP_STEP_ADJOINT:
       if (steps < 0 || ckpt_every < 1) return kInvalid;
       return ws_adjoint(n, steps, ckpt_every, precision);
+    case NBODY_OP_DIAGNOSTICS: return ws_diag(n, precision);
   }
   return kInvalid;
 }
@@ -378,6 +383,30 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
                                 gpos, gvel, gmass, abar, nbody::kAdjFinal, st);
   if (e != hipSuccess) return hip_fail(e, "adjoint combine launch");
   return NBODY_OK;
+}
+
+int nbody_diagnostics(int64_t n, const double *pos, const double *vel,
+                      const double *mass, const nbody_params *p, int precision,
+                      double *out, void *ws, size_t ws_bytes, void *stream) {
+  int rc;
+  if ((rc = check_common(n, p, precision, false))) return rc;
+  if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(vel, "vel")) ||
+      (rc = check_ptr(mass, "mass")) || (rc = check_ptr(out, "out")))
+    return rc;
+  if ((rc = check_ws(ws, ws_bytes, ws_diag(n, precision)))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nn = int(n);
+  const double eps2 = p->eps * p->eps;
+  const Plan pl = nbody::make_plan(nbody::kPotential, precision, n);
+  double *phi = static_cast<double *>(ws);
+  double *blocksum = reinterpret_cast<double *>(static_cast<char *>(ws) +
+                                                dbytes(pl.sj * n));
+  hipError_t e = nbody::launch_potential(pl, precision, nn, pos, mass, eps2,
+                                         phi, st);
+  if (e != hipSuccess) return hip_fail(e, "potential kernel launch");
+  e = nbody::launch_diagnostics(precision, nn, int(pl.sj), phi, pos, vel, mass,
+                                eps2, p->G, blocksum, out, st);
+  return e == hipSuccess ? NBODY_OK : hip_fail(e, "diagnostics launch");
 }
 
 }  // extern "C"

@@ -24,7 +24,7 @@ struct Plan {
   int64_t jchunk;
 };
 
-enum KernelKind { kAccel = 0, kVjp = 1 };
+enum KernelKind { kAccel = 0, kVjp = 1, kPotential = 2 };
 
 Plan make_plan(KernelKind kind, int precision, int64_t n);
 
@@ -74,5 +74,19 @@ hipError_t launch_adj_combine(int n, int sj, const double *part, size_t stride,
                               double G, double dt, double h, double *gpos,
                               double *gvel, double *gmass, double *abar,
                               int mode, hipStream_t st);
+
+// Diagnostics.  launch_potential writes split partials of
+// phi_i = sum_j m_j (|x_j - x_i|^2 + eps^2)^(-1/2) to out[s*n + i];
+// launch_diagnostics reduces them with the O(N) sums into out[9]:
+// K, W, momentum (3), sum m x (3), total mass (blocksum: ceil(n/256)*9
+// doubles of scratch).
+hipError_t launch_potential(const Plan &pl, int precision, int n,
+                            const double *pos, const double *mass, double eps2,
+                            double *out, hipStream_t st);
+hipError_t launch_diagnostics(int precision, int n, int sj,
+                              const double *phi_part, const double *pos,
+                              const double *vel, const double *mass,
+                              double eps2, double G, double *blocksum,
+                              double *out, hipStream_t st);
 
 }  // namespace nbody

@@ -377,6 +377,79 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
   }
 }
 
+// --------------------------------------------------- potential (diagnostic) --
+//
+// phi_i = sum_j m_j (|x_j - x_i|^2 + eps^2)^(-1/2) over all j, written as
+// split partials like the force; the self pair's term m_i rsqrt(eps^2) is
+// removed afterwards by the per-body reduction (self_potential_term).
+
+template <typename T>
+__device__ __forceinline__ double self_potential_term(T m, T eps2) {
+#pragma clang fp contract(off)
+  T y;
+  if constexpr (sizeof(T) == 8) y = rsqrt_f64(eps2); else y = rsqrt_f32(eps2);
+  return double(m) * double(y);  // exact for FP32 operands
+}
+
+template <int PREC, int L>
+__global__ __launch_bounds__(kThreads) void potential_kernel(
+    int n, const double *__restrict__ pos, const double *__restrict__ mass,
+    double eps2d, int jchunk, double *__restrict__ out) {
+  using CT = typename Coord<PREC>::T;
+  using DT = typename Coord<PREC>::D;
+  constexpr int G = kThreads / L;
+  constexpr int PER = kThreads / L;
+  constexpr int C = PER < kChunk ? PER : kChunk;
+  __shared__ Src<PREC> tile[kThreads];
+
+  const int tid = threadIdx.x;
+  const int g = tid / L, q = tid % L;
+  const int i = blockIdx.x * G + g;
+  const int jbeg = blockIdx.y * jchunk;
+  const int jend = min(n, jbeg + jchunk);
+  const bool ok = i < n;
+  const CT xi = ok ? CT(pos[i]) : CT(0);
+  const CT yi = ok ? CT(pos[n + i]) : CT(0);
+  const CT zi = ok ? CT(pos[2 * n + i]) : CT(0);
+  double phi = 0.0;
+
+  for (int jt = jbeg; jt < jend; jt += kThreads) {
+    const int j = jt + tid;
+    const Src<PREC> b = load_src<PREC>(pos, mass, n, j, j < jend);
+    __syncthreads();
+    tile[tid] = b;
+    __syncthreads();
+    if constexpr (PREC == NBODY_FP64) {
+#pragma unroll 4
+      for (int u = 0; u < PER; ++u) {
+        const Src<PREC> s = tile[u * L + q];
+        const double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+        double r2 = fma(dx, dx, eps2d);
+        r2 = fma(dy, dy, r2);
+        r2 = fma(dz, dz, r2);
+        phi = fma(s.m, rsqrt_f64(r2), phi);
+      }
+    } else {
+      const float eps2 = float(eps2d);
+      for (int u0 = 0; u0 < PER; u0 += C) {
+        float f = 0.0f;
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+          const Src<PREC> s = tile[(u0 + u) * L + q];
+          const float dx = DT(s.x - xi), dy = DT(s.y - yi), dz = DT(s.z - zi);
+          float r2 = fmaf(dx, dx, eps2);
+          r2 = fmaf(dy, dy, r2);
+          r2 = fmaf(dz, dz, r2);
+          f = fmaf(s.m, rsqrt_f32(r2), f);
+        }
+        phi += double(f);
+      }
+    }
+  }
+  phi = group_sum<L>(phi);
+  if (q == 0 && ok) out[size_t(blockIdx.y) * n + i] = phi;
+}
+
 // --------------------------------------------------- per-body FP64 kernels --
 //
 // One thread per (component, body): q = c * n + i.  The split partials of
@@ -472,6 +545,66 @@ __global__ __launch_bounds__(kBodyThreads) void adj_combine_kernel(
   }
 }
 
+// Diagnostics, first level: per body the 9 quantities
+//   m|v|^2/2, m (phi - self term), m v (3), m x (3), m
+// summed over the block's bodies by a fixed-order LDS tree into
+// blocksum[blockIdx.x][9].  Second level: one block adds the block sums in
+// ascending order.
+constexpr int kDiag = 9;
+
+template <int PREC>
+__global__ __launch_bounds__(kThreads) void diag_block_kernel(
+    int n, int sj, const double *__restrict__ phi_part,
+    const double *__restrict__ pos, const double *__restrict__ vel,
+    const double *__restrict__ mass, double eps2d,
+    double *__restrict__ blocksum) {
+  using AT = typename Coord<PREC>::D;
+  __shared__ double red[kDiag][kThreads];
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  double v[kDiag];
+#pragma unroll
+  for (int c = 0; c < kDiag; ++c) v[c] = 0.0;
+  if (i < n) {
+    const double m = mass[i];
+    const double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
+    const double phi = split_sum(phi_part, size_t(n), sj, size_t(i)) -
+                       self_potential_term<AT>(AT(m), AT(eps2d));
+    v[0] = 0.5 * m * (vx * vx + vy * vy + vz * vz);
+    v[1] = m * phi;
+    v[2] = m * vx;
+    v[3] = m * vy;
+    v[4] = m * vz;
+    v[5] = m * pos[i];
+    v[6] = m * pos[n + i];
+    v[7] = m * pos[2 * n + i];
+    v[8] = m;
+  }
+#pragma unroll
+  for (int c = 0; c < kDiag; ++c) red[c][threadIdx.x] = v[c];
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int c = 0; c < kDiag; ++c)
+        red[c][threadIdx.x] = red[c][threadIdx.x] + red[c][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kDiag)
+    blocksum[size_t(blockIdx.x) * kDiag + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(64) void diag_final_kernel(
+    int nblocks, const double *__restrict__ blocksum, double G,
+    double *__restrict__ out) {
+  const int c = threadIdx.x;
+  if (c >= kDiag) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += blocksum[size_t(b) * kDiag + c];
+  // out: K, W = -(G/2) sum_i m_i phi_i, momentum (3), sum m x (3), mass
+  out[c] = (c == 1) ? -0.5 * G * s : s;
+}
+
 inline dim3 grid_body(int n, int ncomp) {
   return dim3(unsigned((size_t(ncomp) * n + kBodyThreads - 1) / kBodyThreads));
 }
@@ -531,8 +664,7 @@ Plan make_plan(KernelKind kind, int precision, int64_t n) {
   // resident waves per SIMD, several rounds of them), reached with the
   // smallest lanes-per-target L in {1, 4, 16} that needs at most 64 source
   // splits, each at least one 256-body tile long.
-  (void)kind;
-  const int R = (precision == NBODY_FP64) ? 2 : 1;
+  const int R = (precision == NBODY_FP64 && kind != kPotential) ? 2 : 1;
   const int64_t target = 8192, max_sj = 64;
   const int64_t ntiles = (n + kThreads - 1) / kThreads;
   Plan p{};
@@ -584,6 +716,63 @@ hipError_t launch_vjp(const Plan &pl, int precision, int n, const double *pos,
                                            ox, om, stride, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_potential(const Plan &pl, int precision, int n,
+                            const double *pos, const double *mass, double eps2,
+                            double *out, hipStream_t st) {
+  const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
+  const int jc = int(pl.jchunk);
+#define NBODY_POT(PREC_)                                                      \
+  do {                                                                        \
+    if (pl.L == 1)                                                            \
+      potential_kernel<PREC_, 1><<<grid, kThreads, 0, st>>>(n, pos, mass,     \
+                                                            eps2, jc, out);   \
+    else if (pl.L == 4)                                                       \
+      potential_kernel<PREC_, 4><<<grid, kThreads, 0, st>>>(n, pos, mass,     \
+                                                            eps2, jc, out);   \
+    else if (pl.L == 16)                                                      \
+      potential_kernel<PREC_, 16><<<grid, kThreads, 0, st>>>(n, pos, mass,    \
+                                                             eps2, jc, out);  \
+    else                                                                      \
+      return hipErrorInvalidValue;                                            \
+  } while (0)
+  switch (precision) {
+    case NBODY_FP64: NBODY_POT(NBODY_FP64); break;
+    case NBODY_MIXED: NBODY_POT(NBODY_MIXED); break;
+    case NBODY_MIXED_D64: NBODY_POT(NBODY_MIXED_D64); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef NBODY_POT
+  return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(int precision, int n, int sj,
+                              const double *phi_part, const double *pos,
+                              const double *vel, const double *mass,
+                              double eps2, double G, double *blocksum,
+                              double *out, hipStream_t st) {
+  const int nblocks = (n + kThreads - 1) / kThreads;
+  switch (precision) {
+    case NBODY_FP64:
+      diag_block_kernel<NBODY_FP64><<<nblocks, kThreads, 0, st>>>(
+          n, sj, phi_part, pos, vel, mass, eps2, blocksum);
+      break;
+    case NBODY_MIXED:
+      diag_block_kernel<NBODY_MIXED><<<nblocks, kThreads, 0, st>>>(
+          n, sj, phi_part, pos, vel, mass, eps2, blocksum);
+      break;
+    case NBODY_MIXED_D64:
+      diag_block_kernel<NBODY_MIXED_D64><<<nblocks, kThreads, 0, st>>>(
+          n, sj, phi_part, pos, vel, mass, eps2, blocksum);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  diag_final_kernel<<<1, 64, 0, st>>>(nblocks, blocksum, G, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(int n, int sj, const double *part, size_t stride,
