@@ -417,3 +417,52 @@ def test_half_kick_drift_autograd_rollout(B, dev, oracle):
                                      scheme="half_kick_drift")
     for got, ref in ((P.grad, rx), (V.grad, rv), (M.grad, rm)):
         assert np.linalg.norm(N(got) - ref) / np.linalg.norm(ref) <= 1e-12
+
+
+# ----------------------------------------------------- failure / invariants --
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_nan_position_poisons_without_hanging(B, dev, prec):
+    # a NaN coordinate makes every acceleration that sums over it NaN (all of
+    # them: every body sees every source) and the call still returns
+    say("nan propagation", prec)
+    pos, _, mass = inputs.uniform_cube(1000, 71)
+    pos[1, 17] = np.nan
+    a = N(B.nbody_accel(T(pos, dev), T(mass, dev), 1.0, 1e-3, prec))
+    assert np.isnan(a).any(axis=0).all()
+    # the rest of the library keeps working afterwards
+    pos2, _, mass2 = inputs.uniform_cube(300, 72)
+    assert np.isfinite(N(B.nbody_accel(T(pos2, dev), T(mass2, dev), 1.0, 1e-3, prec))).all()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_translation_invariance(B, dev, prec):
+    say("translation", prec)
+    pos, _, mass = inputs.uniform_cube(2000, 73)
+    # on a 2^-20 grid with |x| < 2 every position, shifted position and
+    # difference is exact in FP32 and FP64, so every pair term, and therefore
+    # the fixed-order sum, is bitwise the same after the shift
+    pos = np.round(pos * 2.0 ** 20) / 2.0 ** 20
+    shift = np.array([[0.25], [-0.5], [0.125]])
+    a0 = N(B.nbody_accel(T(pos, dev), T(mass, dev), 1.0, 1e-3, prec))
+    a1 = N(B.nbody_accel(T(pos + shift, dev), T(mass, dev), 1.0, 1e-3, prec))
+    assert np.array_equal(a0, a1)
+
+
+def test_vjp_dot_product_test_fp64(B, dev):
+    # <gbar, J dx> by central differences of the GPU forward equals
+    # <J^T gbar, dx> from the GPU VJP (both FP64).
+    say("vjp dot-product")
+    n = 512
+    pos, _, mass = inputs.uniform_cube(n, 74)
+    g = inputs.upstream_normal(n, 75)
+    dx = inputs.upstream_normal(n, 76)
+    dm = inputs.upstream_normal(n, 77)[0] * mass
+    gx, gm = B.nbody_accel_vjp(T(pos, dev), T(mass, dev), T(g, dev), 1.0, 1e-2, "fp64")
+    h = 1e-6
+
+    def L(p, m):
+        return float((g * N(B.nbody_accel(T(p, dev), T(m, dev), 1.0, 1e-2, "fp64"))).sum())
+    fd = (L(pos + h * dx, mass + h * dm) - L(pos - h * dx, mass - h * dm)) / (2 * h)
+    ad = float((N(gx) * dx).sum() + (N(gm) * dm).sum())
+    assert fd == pytest.approx(ad, rel=1e-6)
