@@ -50,7 +50,7 @@ FLOPS_PER_PAIR = {"accel": 20, "vjp": 48, "diag": 13}
 # 64 MiB device copy; profiles/vjp_kernel_cube16384_mixed_traffic.md).  They
 # describe the kernel source they were taken on (first 16 hex digits of its
 # SHA-256) and are reported as null for any other source.
-MEASURED_TRAFFIC = {("vjp", "mixed"): {"bytes": 24.2e6, "src_sha256": "67cc9fe81b02bdb6"}}
+MEASURED_TRAFFIC = {("vjp", "mixed"): {"bytes": 24.2e6, "src_sha256": "84cc4c1565e625bd"}}
 KERNEL_SRC = os.path.join(ROOT, "paper_2203_08263_amd", "csrc", "nbody_kernels.hip")
 DTYPE = {"fp64": "f64", "mixed": "f32-pair/f64-acc",
          "mixed_d64": "f32-pair(f64-diff)/f64-acc"}
@@ -174,37 +174,55 @@ def shape_legs(torch, B, inputs):
     and the energy diagnostics at N = 65536 (Plummer, a = 1, eps = 1e-2) and
     the forward and VJP at N = 262144 (clustered Plummer, a = 0.1,
     eps = 1e-3), each timed with HIP events over back-to-back calls (kernel +
-    split reduce)."""
+    split reduce).  At N = 262144 also one device's share when the target rows
+    are split eight ways (rows 3/8 .. 4/8 against all sources, the row-range
+    entry points), the per-device kernel shape of that partition."""
     dev = torch.device("cuda:0")
     T = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa
     out = {}
     for name, precs, kinds in (("plummer65536", ("mixed", "mixed_d64", "fp64"),
                                 ("accel", "diag")),
                                ("plummer262144_vjp", ("mixed", "mixed_d64", "fp64"),
-                                ("accel", "vjp"))):
+                                ("accel", "vjp", "accel_share8", "vjp_share8"))):
         w = inputs.WORKLOADS[name]
         pos, vel, mass = w.initial_state()
         P, M, Vt = T(pos), T(mass), T(vel)
         D = torch.empty(9, dtype=torch.float64, device=dev)
         Gt = T(inputs.upstream_normal(w.n, w.seed + 400))
         A, GX, GM = torch.empty_like(P), torch.empty_like(P), torch.empty_like(M)
+        share = w.n // 8
+        r0 = 3 * share
+        As = torch.empty((3, share), dtype=torch.float64, device=dev)
+        GXs = torch.empty((3, share), dtype=torch.float64, device=dev)
+        GMs = torch.empty(share, dtype=torch.float64, device=dev)
         res = {}
         for p in precs:
             ws = torch.empty(max(B.nbody_workspace_bytes(B.NBODY_OP_ACCEL, w.n, 0, 1, p),
                                  B.nbody_workspace_bytes(B.NBODY_OP_VJP, w.n, 0, 1, p),
                                  B.nbody_workspace_bytes(B.NBODY_OP_DIAGNOSTICS, w.n, 0, 1,
-                                                         p), 256),
+                                                         p),
+                                 B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, w.n, share, p),
+                                 B.nbody_rows_workspace_bytes(B.NBODY_OP_VJP, w.n, share, p),
+                                 256),
                              dtype=torch.uint8, device=dev)
             for kind in kinds:
                 if kind == "accel":
                     fn = lambda: B.nbody_accel(P, M, w.G, w.eps, p, out=A, workspace=ws)  # noqa
+                elif kind == "accel_share8":
+                    fn = lambda: B.nbody_accel_rows(P, M, r0, share, w.G, w.eps, p,  # noqa
+                                                    out=As, workspace=ws)
+                elif kind == "vjp_share8":
+                    fn = lambda: B.nbody_accel_vjp_rows(  # noqa
+                        P, M, Gt, r0, share, w.G, w.eps, p, gpos=GXs, gmass=GMs,
+                        workspace=ws)
                 elif kind == "diag":
                     fn = lambda: B.nbody_diagnostics(P, Vt, M, w.G, w.eps, p, out=D,  # noqa
                                                      workspace=ws)
                 else:
                     fn = lambda: B.nbody_accel_vjp(P, M, Gt, w.G, w.eps, p, gpos=GX,  # noqa
                                                    gmass=GM, workspace=ws)
-                reps = 20 if w.n <= 65536 else 4
+                rows = share if kind.endswith("_share8") else w.n
+                reps = 20 if w.n <= 65536 else (16 if rows < w.n else 4)
                 warm(torch, fn)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
@@ -213,12 +231,13 @@ def shape_legs(torch, B, inputs):
                 e1.record()
                 torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1) / reps
-                ips = float(w.n) * w.n / (ms * 1e-3)
+                ips = float(rows) * w.n / (ms * 1e-3)
                 peak = PEAK_FP64_TFLOPS if p == "fp64" else PEAK_FP32_TFLOPS
+                fl = FLOPS_PER_PAIR[kind.replace("_share8", "")]
                 res["%s_%s" % (kind, p)] = {
                     "ms": round(ms, 4), "G_int_s": round(ips / 1e9, 1),
-                    "TFLOP_s": round(ips * FLOPS_PER_PAIR[kind] / 1e12, 2),
-                    "frac_of_vector_peak": round(ips * FLOPS_PER_PAIR[kind] / 1e12 / peak, 4)}
+                    "TFLOP_s": round(ips * fl / 1e12, 2),
+                    "frac_of_vector_peak": round(ips * fl / 1e12 / peak, 4)}
         if "vjp_mixed" in res:
             for p in precs:
                 res["vjp_over_fwd_%s" % p] = round(res["vjp_%s" % p]["ms"] /

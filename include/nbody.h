@@ -32,8 +32,9 @@
  *    the calling thread's most recent failure.  No call prints, throws or
  *    exits.
  *  - Determinism: no atomics are used; every sum is taken in a fixed order
- *    that depends only on (n, precision).  Repeated calls with the same
- *    inputs give bitwise identical results.
+ *    that depends only on (n, precision) (and the row count, for the
+ *    row-range calls).  Repeated calls with the same inputs give bitwise
+ *    identical results.
  *  - Interactions: one force evaluation visits all n*n ordered pairs,
  *    including j == i, whose contribution is exactly zero since eps > 0.
  */
@@ -219,6 +220,45 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
 int nbody_diagnostics(int64_t n, const double *pos, const double *vel,
                       const double *mass, const nbody_params *p, int precision,
                       double *out, void *ws, size_t ws_bytes, void *stream);
+
+/* Row ranges.  The force sum and its VJP for the target bodies
+ * row_begin .. row_begin + row_count - 1 of an n-body system, against all n
+ * sources: the share of one device when the target rows of the section 2.3
+ * sum are divided among devices that each hold every body's position and
+ * mass (and dL/da).  Outputs have row_count rows: a "row vector" is 3 *
+ * row_count doubles, component-major with stride row_count, and a "row
+ * scalar" row_count doubles; output row r belongs to body row_begin + r.
+ * With row_begin = 0 and row_count = n the results are bitwise those of
+ * nbody_accel / nbody_accel_vjp.  row_count == 0 is a valid no-op: nothing
+ * is enqueued and the array pointers are not examined.
+ *
+ * Workspace bytes for op NBODY_OP_ACCEL or NBODY_OP_VJP on row_count target
+ * rows; (size_t)-1 for any other op or invalid arguments. */
+size_t nbody_rows_workspace_bytes(int op, int64_t n, int64_t row_count,
+                                  int precision);
+
+/* a_i (as nbody_accel) for i = row_begin .. row_begin + row_count - 1.
+ *  pos  [vector] in   all n positions;  mass [scalar] in  all n masses
+ *  acc  [row vector] out
+ *  ws   >= nbody_rows_workspace_bytes(NBODY_OP_ACCEL, n, row_count, precision)
+ * Errors: as nbody_accel, plus row_begin < 0, row_count < 0 or
+ * row_begin + row_count > n. */
+int nbody_accel_rows(int64_t n, int64_t row_begin, int64_t row_count,
+                     const double *pos, const double *mass, double *acc,
+                     const nbody_params *p, int precision, void *ws,
+                     size_t ws_bytes, void *stream);
+
+/* dL/dx_k and dL/dm_k (as nbody_accel_vjp) for k = row_begin .. row_begin +
+ * row_count - 1; every source j contributes through gbar_j and gbar_k.
+ *  pos, mass [all n] in;  gacc [vector] in  dL/da of all n bodies
+ *  gpos [row vector] out;  gmass [row scalar] out
+ *  ws   >= nbody_rows_workspace_bytes(NBODY_OP_VJP, n, row_count, precision)
+ * Errors: as nbody_accel_rows. */
+int nbody_accel_vjp_rows(int64_t n, int64_t row_begin, int64_t row_count,
+                         const double *pos, const double *mass,
+                         const double *gacc, double *gpos, double *gmass,
+                         const nbody_params *p, int precision, void *ws,
+                         size_t ws_bytes, void *stream);
 
 /* Static description of a status code (never NULL). */
 const char *nbody_error_string(int code);

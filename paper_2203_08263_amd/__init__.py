@@ -14,8 +14,9 @@ import importlib
 _BINDING = (
     "NBODY_FP64", "NBODY_MIXED", "NBODY_MIXED_D64", "PRECISIONS", "NBodyError",
     "nbody_accel", "nbody_accel_vjp", "nbody_step", "nbody_step_adjoint",
-    "nbody_diagnostics", "nbody_workspace_bytes", "nbody_checkpoint_bytes",
-    "library_path",
+    "nbody_diagnostics", "nbody_accel_rows", "nbody_accel_vjp_rows",
+    "nbody_workspace_bytes", "nbody_rows_workspace_bytes",
+    "nbody_checkpoint_bytes", "library_path",
     "load_library",
 )
 _AUTOGRAD = ("NBodyAccel", "NBodyRollout", "accel", "rollout")

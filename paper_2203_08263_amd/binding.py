@@ -33,7 +33,9 @@ NBODY_MAX_N = 1 << 28
 
 SYMBOLS = ("nbody_workspace_bytes", "nbody_checkpoint_bytes", "nbody_accel",
            "nbody_step", "nbody_accel_vjp", "nbody_step_adjoint",
-           "nbody_diagnostics", "nbody_error_string", "nbody_last_error")
+           "nbody_diagnostics", "nbody_rows_workspace_bytes",
+           "nbody_accel_rows", "nbody_accel_vjp_rows", "nbody_error_string",
+           "nbody_last_error")
 
 _INVALID = ctypes.c_size_t(-1).value
 
@@ -80,8 +82,14 @@ def load_library():
     lib.nbody_step_adjoint.argtypes = [i64, i64, i64, vp, vp, pp, ci,
                                        ctypes.c_uint, vp, vp, vp, vp, vp, sz, vp]
     lib.nbody_diagnostics.argtypes = [i64, vp, vp, vp, pp, ci, vp, vp, sz, vp]
+    lib.nbody_rows_workspace_bytes.argtypes = [ci, i64, i64, ci]
+    lib.nbody_rows_workspace_bytes.restype = sz
+    lib.nbody_accel_rows.argtypes = [i64, i64, i64, vp, vp, vp, pp, ci, vp, sz, vp]
+    lib.nbody_accel_vjp_rows.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, pp, ci,
+                                         vp, sz, vp]
     for f in ("nbody_accel", "nbody_step", "nbody_accel_vjp",
-              "nbody_step_adjoint", "nbody_diagnostics"):
+              "nbody_step_adjoint", "nbody_diagnostics", "nbody_accel_rows",
+              "nbody_accel_vjp_rows"):
         getattr(lib, f).restype = ci
     lib.nbody_error_string.argtypes = [ci]
     lib.nbody_error_string.restype = ctypes.c_char_p
@@ -154,6 +162,12 @@ def nbody_workspace_bytes(op: int, n: int, steps: int = 0, ckpt_every: int = 1,
                           precision=NBODY_FP64) -> int:
     return int(load_library().nbody_workspace_bytes(op, n, steps, ckpt_every,
                                                     _precision(precision)))
+
+
+def nbody_rows_workspace_bytes(op: int, n: int, row_count: int,
+                               precision=NBODY_FP64) -> int:
+    return int(load_library().nbody_rows_workspace_bytes(op, n, row_count,
+                                                         _precision(precision)))
 
 
 def nbody_checkpoint_bytes(n: int, steps: int, ckpt_every: int) -> int:
@@ -295,3 +309,55 @@ def nbody_diagnostics(pos, vel, mass, G=1.0, eps=1e-3, precision=NBODY_FP64,
     _check(lib.nbody_diagnostics(n, _ptr(pos), _ptr(vel), _ptr(mass), ctypes.byref(prm),
                                  prec, _ptr(out), _ptr(ws), wsb, _stream(dev)))
     return out
+
+
+def _rows_out(t, rows, shape, name, dev):
+    if t is None:
+        return torch.empty(shape, dtype=torch.float64, device=dev)
+    return _vec(t, rows, name, dev) if len(shape) == 2 else _scal(t, rows, name, dev)
+
+
+def nbody_accel_rows(pos, mass, row_begin, row_count, G=1.0, eps=1e-3,
+                     precision=NBODY_FP64, out=None, workspace=None):
+    """Accelerations (3, row_count) of bodies row_begin .. row_begin +
+    row_count - 1 against all n sources."""
+    lib = load_library()
+    n = mass.shape[0]
+    dev = mass.device
+    _scal(mass, n, "mass")
+    _vec(pos, n, "pos", dev)
+    prec = _precision(precision)
+    rows = int(row_count)
+    acc = _rows_out(out, rows, (3, rows), "out", dev)
+    ws, wsb = _workspace(lib.nbody_rows_workspace_bytes(NBODY_OP_ACCEL, n, rows,
+                                                        prec), dev, workspace)
+    prm = _Params(G, eps, 0.0)
+    _check(lib.nbody_accel_rows(n, int(row_begin), rows, _ptr(pos), _ptr(mass),
+                                _ptr(acc), ctypes.byref(prm), prec, _ptr(ws), wsb,
+                                _stream(dev)))
+    return acc
+
+
+def nbody_accel_vjp_rows(pos, mass, gacc, row_begin, row_count, G=1.0, eps=1e-3,
+                         precision=NBODY_FP64, gpos=None, gmass=None,
+                         workspace=None):
+    """(dL/dx (3, row_count), dL/dm (row_count,)) of bodies row_begin ..
+    row_begin + row_count - 1, for upstream gacc = dL/da of all n bodies."""
+    lib = load_library()
+    n = mass.shape[0]
+    dev = mass.device
+    _scal(mass, n, "mass")
+    _vec(pos, n, "pos", dev)
+    _vec(gacc, n, "gacc", dev)
+    prec = _precision(precision)
+    rows = int(row_count)
+    gpos = _rows_out(gpos, rows, (3, rows), "gpos", dev)
+    gmass = _rows_out(gmass, rows, (rows,), "gmass", dev)
+    ws, wsb = _workspace(lib.nbody_rows_workspace_bytes(NBODY_OP_VJP, n, rows,
+                                                        prec), dev, workspace)
+    prm = _Params(G, eps, 0.0)
+    _check(lib.nbody_accel_vjp_rows(n, int(row_begin), rows, _ptr(pos), _ptr(mass),
+                                    _ptr(gacc), _ptr(gpos), _ptr(gmass),
+                                    ctypes.byref(prm), prec, _ptr(ws), wsb,
+                                    _stream(dev)))
+    return gpos, gmass

@@ -98,6 +98,16 @@ size_t ws_diag(int64_t n, int prec) {
   const Plan pl = nbody::make_plan(nbody::kPotential, prec, n);
   return dbytes(pl.sj * n) + dbytes(((n + nbody::kThreads - 1) / nbody::kThreads) * 9);
 }
+size_t ws_accel_rows(int64_t n, int64_t nt, int prec) {
+  if (nt == 0) return 0;
+  const Plan pl = nbody::make_plan(nbody::kAccel, prec, nt, n);
+  return pl.sj > 1 ? dbytes(pl.sj * 3 * nt) : 0;
+}
+size_t ws_vjp_rows(int64_t n, int64_t nt, int prec) {
+  if (nt == 0) return 0;
+  const Plan pl = nbody::make_plan(nbody::kVjp, prec, nt, n);
+  return pl.sj > 1 ? dbytes(pl.sj * 4 * nt) : 0;
+}
 size_t ws_part_adjoint(int64_t n, int prec) {
   const Plan pf = nbody::make_plan(nbody::kAccel, prec, n);
   const Plan pv = nbody::make_plan(nbody::kVjp, prec, n);
@@ -109,6 +119,16 @@ size_t ws_adjoint(int64_t n, int64_t steps, int64_t K, int prec) {
   return 3 * dbytes(3 * n) + dbytes(seg * 3 * n) + ws_part_adjoint(n, prec);
 }
 
+int check_rows(int64_t n, int64_t row_begin, int64_t row_count) {
+  if (row_begin < 0 || row_count < 0 || row_begin > n ||
+      row_count > n - row_begin)
+    return fail(NBODY_ERR_INVALID_ARGUMENT,
+                "rows [%lld, %lld + %lld) outside [0, n = %lld)",
+                (long long)row_begin, (long long)row_begin,
+                (long long)row_count, (long long)n);
+  return NBODY_OK;
+}
+
 int64_t num_records(int64_t steps, int64_t K) {
   return std::max<int64_t>(1, (steps + K - 1) / K);
 }
@@ -118,8 +138,8 @@ int64_t num_records(int64_t steps, int64_t K) {
 int accel_to_parts(const Plan &pl, int prec, int n, const double *pos,
                    const double *mass, double eps2, double *part,
                    hipStream_t st) {
-  hipError_t e = nbody::launch_accel(pl, prec, n, pos, mass, eps2, 1.0, part,
-                                     size_t(3) * n, st);
+  hipError_t e = nbody::launch_accel(pl, prec, n, 0, n, pos, mass, eps2, 1.0,
+                                     part, size_t(3) * n, st);
   return e == hipSuccess ? NBODY_OK : hip_fail(e, "accel kernel launch");
 }
 
@@ -155,6 +175,18 @@ size_t nbody_workspace_bytes(int op, int64_t n, int64_t steps,
   return kInvalid;
 }
 
+size_t nbody_rows_workspace_bytes(int op, int64_t n, int64_t row_count,
+                                  int precision) {
+  if (n < 1 || n > NBODY_MAX_N || !valid_precision(precision) ||
+      row_count < 0 || row_count > n)
+    return kInvalid;
+  switch (op) {
+    case NBODY_OP_ACCEL: return ws_accel_rows(n, row_count, precision);
+    case NBODY_OP_VJP: return ws_vjp_rows(n, row_count, precision);
+  }
+  return kInvalid;
+}
+
 size_t nbody_checkpoint_bytes(int64_t n, int64_t steps, int64_t ckpt_every) {
   if (n < 1 || n > NBODY_MAX_N || steps < 0 || ckpt_every < 1) return kInvalid;
   return size_t(num_records(steps, ckpt_every)) * 9 * size_t(n) *
@@ -176,8 +208,8 @@ int nbody_accel(int64_t n, const double *pos, const double *mass, double *acc,
   const Plan pl = nbody::make_plan(nbody::kAccel, precision, n);
   hipError_t e;
   if (pl.sj == 1) {
-    e = nbody::launch_accel(pl, precision, nn, pos, mass, eps2, p->G, acc, 0,
-                            st);
+    e = nbody::launch_accel(pl, precision, nn, 0, nn, pos, mass, eps2, p->G,
+                            acc, 0, st);
     if (e != hipSuccess) return hip_fail(e, "accel kernel launch");
     return NBODY_OK;
   }
@@ -186,6 +218,73 @@ int nbody_accel(int64_t n, const double *pos, const double *mass, double *acc,
     return rc;
   e = nbody::launch_reduce(nn, int(pl.sj), part, size_t(3) * n, p->G, acc,
                            nullptr, st);
+  return e == hipSuccess ? NBODY_OK : hip_fail(e, "reduce kernel launch");
+}
+
+int nbody_accel_rows(int64_t n, int64_t row_begin, int64_t row_count,
+                     const double *pos, const double *mass, double *acc,
+                     const nbody_params *p, int precision, void *ws,
+                     size_t ws_bytes, void *stream) {
+  int rc;
+  if ((rc = check_common(n, p, precision, false))) return rc;
+  if ((rc = check_rows(n, row_begin, row_count))) return rc;
+  if (row_count == 0) return NBODY_OK;
+  if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(mass, "mass")) ||
+      (rc = check_ptr(acc, "acc")))
+    return rc;
+  if ((rc = check_ws(ws, ws_bytes, ws_accel_rows(n, row_count, precision))))
+    return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nn = int(n), r0 = int(row_begin), nt = int(row_count);
+  const double eps2 = p->eps * p->eps;
+  const Plan pl = nbody::make_plan(nbody::kAccel, precision, row_count, n);
+  hipError_t e;
+  if (pl.sj == 1) {
+    e = nbody::launch_accel(pl, precision, nn, r0, nt, pos, mass, eps2, p->G,
+                            acc, 0, st);
+    return e == hipSuccess ? NBODY_OK : hip_fail(e, "accel kernel launch");
+  }
+  double *part = static_cast<double *>(ws);
+  e = nbody::launch_accel(pl, precision, nn, r0, nt, pos, mass, eps2, 1.0,
+                          part, size_t(3) * nt, st);
+  if (e != hipSuccess) return hip_fail(e, "accel kernel launch");
+  e = nbody::launch_reduce(nt, int(pl.sj), part, size_t(3) * nt, p->G, acc,
+                           nullptr, st);
+  return e == hipSuccess ? NBODY_OK : hip_fail(e, "reduce kernel launch");
+}
+
+int nbody_accel_vjp_rows(int64_t n, int64_t row_begin, int64_t row_count,
+                         const double *pos, const double *mass,
+                         const double *gacc, double *gpos, double *gmass,
+                         const nbody_params *p, int precision, void *ws,
+                         size_t ws_bytes, void *stream) {
+  int rc;
+  if ((rc = check_common(n, p, precision, false))) return rc;
+  if ((rc = check_rows(n, row_begin, row_count))) return rc;
+  if (row_count == 0) return NBODY_OK;
+  if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(mass, "mass")) ||
+      (rc = check_ptr(gacc, "gacc")) || (rc = check_ptr(gpos, "gpos")) ||
+      (rc = check_ptr(gmass, "gmass")))
+    return rc;
+  if ((rc = check_ws(ws, ws_bytes, ws_vjp_rows(n, row_count, precision))))
+    return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nn = int(n), r0 = int(row_begin), nt = int(row_count);
+  const double eps2 = p->eps * p->eps;
+  const Plan pl = nbody::make_plan(nbody::kVjp, precision, row_count, n);
+  hipError_t e;
+  if (pl.sj == 1) {
+    e = nbody::launch_vjp(pl, precision, nn, r0, nt, pos, mass, gacc, eps2,
+                          p->G, gpos, gmass, 0, st);
+    return e == hipSuccess ? NBODY_OK : hip_fail(e, "vjp kernel launch");
+  }
+  double *part = static_cast<double *>(ws);
+  const size_t stride = size_t(4) * nt;
+  e = nbody::launch_vjp(pl, precision, nn, r0, nt, pos, mass, gacc, eps2, 1.0,
+                        part, part + size_t(3) * nt, stride, st);
+  if (e != hipSuccess) return hip_fail(e, "vjp kernel launch");
+  e = nbody::launch_reduce(nt, int(pl.sj), part, stride, p->G, gpos, gmass,
+                           st);
   return e == hipSuccess ? NBODY_OK : hip_fail(e, "reduce kernel launch");
 }
 
@@ -270,14 +369,14 @@ int nbody_accel_vjp(int64_t n, const double *pos, const double *mass,
   const Plan pl = nbody::make_plan(nbody::kVjp, precision, n);
   hipError_t e;
   if (pl.sj == 1) {
-    e = nbody::launch_vjp(pl, precision, nn, pos, mass, gacc, eps2, p->G, gpos,
-                          gmass, 0, st);
+    e = nbody::launch_vjp(pl, precision, nn, 0, nn, pos, mass, gacc, eps2, p->G,
+                          gpos, gmass, 0, st);
     return e == hipSuccess ? NBODY_OK : hip_fail(e, "vjp kernel launch");
   }
   double *part = static_cast<double *>(ws);
   const size_t stride = size_t(4) * n;
-  e = nbody::launch_vjp(pl, precision, nn, pos, mass, gacc, eps2, 1.0, part,
-                        part + size_t(3) * n, stride, st);
+  e = nbody::launch_vjp(pl, precision, nn, 0, nn, pos, mass, gacc, eps2, 1.0,
+                        part, part + size_t(3) * n, stride, st);
   if (e != hipSuccess) return hip_fail(e, "vjp kernel launch");
   e = nbody::launch_reduce(nn, int(pl.sj), part, stride, p->G, gpos, gmass, st);
   return e == hipSuccess ? NBODY_OK : hip_fail(e, "reduce kernel launch");
@@ -362,8 +461,8 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
     // Reverse sweep over steps s0+k-1 .. s0: VJP at x_{t+1} = seg[t - s0].
     for (int64_t t = s0 + k - 1; t >= s0; --t) {
       const double *xt1 = seg + size_t(t - s0) * q3;
-      e = nbody::launch_vjp(pv, precision, nn, xt1, mass, abar, eps2, 1.0,
-                            part, part + q3, size_t(4) * n, st);
+      e = nbody::launch_vjp(pv, precision, nn, 0, nn, xt1, mass, abar, eps2,
+                            1.0, part, part + q3, size_t(4) * n, st);
       if (e != hipSuccess) return hip_fail(e, "vjp kernel launch");
       // abar_t = (dt/2) vbar from the opening half-kick of step t, plus the
       // closing half-kick of step t-1 under kick-drift-kick.
@@ -376,8 +475,8 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
     }
   }
   // a_0 = A(x_0): final VJP at the initial positions (checkpoint record 0).
-  e = nbody::launch_vjp(pv, precision, nn, ckpt, mass, abar, eps2, 1.0, part,
-                        part + q3, size_t(4) * n, st);
+  e = nbody::launch_vjp(pv, precision, nn, 0, nn, ckpt, mass, abar, eps2, 1.0,
+                        part, part + q3, size_t(4) * n, st);
   if (e != hipSuccess) return hip_fail(e, "vjp kernel launch");
   e = nbody::launch_adj_combine(nn, int(pv.sj), part, size_t(4) * n, G, dt, h,
                                 gpos, gvel, gmass, abar, nbody::kAdjFinal, st);

@@ -14,7 +14,7 @@ constexpr int kThreads = 256;
 // Launch plan of one all-pairs kernel: L lanes share each target body and
 // each lane group serves R targets, so a workgroup owns (kThreads/L)*R
 // targets; n_ib target blocks; sj source splits of jchunk bodies (jchunk a
-// multiple of kThreads).  Depends only on (kind, precision, n), so a
+// multiple of kThreads).  Depends only on (kind, precision, nt, n), so a
 // recomputation reproduces every partial sum bitwise.
 struct Plan {
   int R;
@@ -26,19 +26,26 @@ struct Plan {
 
 enum KernelKind { kAccel = 0, kVjp = 1, kPotential = 2 };
 
+// Plan for nt target rows against n source bodies; the one-argument form is
+// the whole system (nt = n).
 Plan make_plan(KernelKind kind, int precision, int64_t n);
+Plan make_plan(KernelKind kind, int precision, int64_t nt, int64_t n);
 
-// out + s*split_stride + c*n + i  <-  scale * sum over source split s of the
-// acceleration sum (without G when scale == 1), c = 0..2.
-hipError_t launch_accel(const Plan &pl, int precision, int n, const double *pos,
-                        const double *mass, double eps2, double scale,
-                        double *out, size_t split_stride, hipStream_t st);
+// Targets are bodies row0 .. row0 + nt - 1 of the n-body system (pos is
+// [3][n]), sources all n bodies; plan from make_plan(kind, precision, nt, n).
+// out + s*split_stride + c*nt + i  <-  scale * sum over source split s of the
+// acceleration sum of body row0 + i (without G when scale == 1), c = 0..2.
+hipError_t launch_accel(const Plan &pl, int precision, int n, int row0, int nt,
+                        const double *pos, const double *mass, double eps2,
+                        double scale, double *out, size_t split_stride,
+                        hipStream_t st);
 
-// out_x + s*stride + c*n + i <- scale * sum_j [s^-3/2 h - 3 s^-5/2 (e.h) e],
-// out_m + s*stride + i       <- -scale * sum_j (gbar_j . e) s^-3/2.
-hipError_t launch_vjp(const Plan &pl, int precision, int n, const double *pos,
-                      const double *mass, const double *gacc, double eps2,
-                      double scale, double *out_x, double *out_m,
+// Rows as launch_accel, gacc [3][n]:
+// out_x + s*stride + c*nt + i <- scale * sum_j [s^-3/2 h - 3 s^-5/2 (e.h) e],
+// out_m + s*stride + i        <- -scale * sum_j (gbar_j . e) s^-3/2.
+hipError_t launch_vjp(const Plan &pl, int precision, int n, int row0, int nt,
+                      const double *pos, const double *mass, const double *gacc,
+                      double eps2, double scale, double *out_x, double *out_m,
                       size_t split_stride, hipStream_t st);
 
 // out_x[c*n+i] = G * sum_s part[s*stride + c*n + i], c < 3; if out_m:

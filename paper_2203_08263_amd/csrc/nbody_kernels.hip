@@ -176,12 +176,16 @@ __device__ __forceinline__ double group_sum(double v) {
 // and lane q visits the tile entries q, q + L, q + 2L, ...  With L > 1 a
 // small system still yields enough waves without splitting the source range
 // into many FP64 partials.
+//
+// Targets are the nt bodies row0 .. row0 + nt - 1 of the n-body system (all
+// of it when row0 = 0, nt = n), sources are all n bodies; output row i (of
+// stride nt) belongs to body row0 + i.
 
 template <int PREC, int R, int L>
 __global__ __launch_bounds__(kThreads) void accel_kernel(
-    int n, const double *__restrict__ pos, const double *__restrict__ mass,
-    double eps2d, double scale, int jchunk, double *__restrict__ out,
-    size_t split_stride) {
+    int n, int row0, int nt, const double *__restrict__ pos,
+    const double *__restrict__ mass, double eps2d, double scale, int jchunk,
+    double *__restrict__ out, size_t split_stride) {
   using CT = typename Coord<PREC>::T;
   using DT = typename Coord<PREC>::D;
   constexpr int G = kThreads / L;             // target groups per workgroup
@@ -200,10 +204,11 @@ __global__ __launch_bounds__(kThreads) void accel_kernel(
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = ibase + r * G;
-    const bool ok = i < n;
-    xi[r] = ok ? CT(pos[i]) : CT(0);
-    yi[r] = ok ? CT(pos[n + i]) : CT(0);
-    zi[r] = ok ? CT(pos[2 * n + i]) : CT(0);
+    const bool ok = i < nt;
+    const int gi = row0 + i;
+    xi[r] = ok ? CT(pos[gi]) : CT(0);
+    yi[r] = ok ? CT(pos[n + gi]) : CT(0);
+    zi[r] = ok ? CT(pos[2 * n + gi]) : CT(0);
     ax[r] = ay[r] = az[r] = 0.0;
   }
 
@@ -254,22 +259,24 @@ __global__ __launch_bounds__(kThreads) void accel_kernel(
     const double sy = group_sum<L>(ay[r]);
     const double sz = group_sum<L>(az[r]);
     const int i = ibase + r * G;
-    if (q == 0 && i < n) {
+    if (q == 0 && i < nt) {
       o[i] = scale * sx;
-      o[n + i] = scale * sy;
-      o[2 * n + i] = scale * sz;
+      o[nt + i] = scale * sy;
+      o[2 * nt + i] = scale * sz;
     }
   }
 }
 
 // ---------------------------------------------------------------------- VJP --
 
+// Rows as in accel_kernel: targets k = row0 .. row0 + nt - 1, sources all n
+// bodies (with their dL/da), output row k - row0 of stride nt.
 template <int PREC, int R, int L>
 __global__ __launch_bounds__(kThreads) void vjp_kernel(
-    int n, const double *__restrict__ pos, const double *__restrict__ mass,
-    const double *__restrict__ gacc, double eps2d, double scale, int jchunk,
-    double *__restrict__ out_x, double *__restrict__ out_m,
-    size_t split_stride) {
+    int n, int row0, int nt, const double *__restrict__ pos,
+    const double *__restrict__ mass, const double *__restrict__ gacc,
+    double eps2d, double scale, int jchunk, double *__restrict__ out_x,
+    double *__restrict__ out_m, size_t split_stride) {
   using CT = typename Coord<PREC>::T;
   using DT = typename Coord<PREC>::D;
   using AT = typename Coord<PREC>::D;  // arithmetic type of the pair terms
@@ -290,14 +297,15 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int k = kbase + r * G;
-    const bool ok = k < n;
-    xk[r] = ok ? CT(pos[k]) : CT(0);
-    yk[r] = ok ? CT(pos[n + k]) : CT(0);
-    zk[r] = ok ? CT(pos[2 * n + k]) : CT(0);
-    mk[r] = ok ? AT(mass[k]) : AT(0);
-    gkx[r] = ok ? AT(gacc[k]) : AT(0);
-    gky[r] = ok ? AT(gacc[n + k]) : AT(0);
-    gkz[r] = ok ? AT(gacc[2 * n + k]) : AT(0);
+    const bool ok = k < nt;
+    const int gk = row0 + k;
+    xk[r] = ok ? CT(pos[gk]) : CT(0);
+    yk[r] = ok ? CT(pos[n + gk]) : CT(0);
+    zk[r] = ok ? CT(pos[2 * n + gk]) : CT(0);
+    mk[r] = ok ? AT(mass[gk]) : AT(0);
+    gkx[r] = ok ? AT(gacc[gk]) : AT(0);
+    gky[r] = ok ? AT(gacc[n + gk]) : AT(0);
+    gkz[r] = ok ? AT(gacc[2 * n + gk]) : AT(0);
     sx[r] = sy[r] = sz[r] = sm[r] = 0.0;
   }
 
@@ -363,15 +371,16 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
     double tz = group_sum<L>(sz[r]);
     const double tm = group_sum<L>(sm[r]);
     const int k = kbase + r * G;
-    if (q == 0 && k < n) {
-      if (k >= jbeg && k < jend) {  // this split holds the self pair
+    const int gk = row0 + k;
+    if (q == 0 && k < nt) {
+      if (gk >= jbeg && gk < jend) {  // this split holds the self pair
         tx -= self_pair_term<AT>(mk[r], gkx[r], eps2a);
         ty -= self_pair_term<AT>(mk[r], gky[r], eps2a);
         tz -= self_pair_term<AT>(mk[r], gkz[r], eps2a);
       }
       ox[k] = scale * tx;
-      ox[n + k] = scale * ty;
-      ox[2 * n + k] = scale * tz;
+      ox[nt + k] = scale * ty;
+      ox[2 * nt + k] = scale * tz;
       om[k] = -scale * tm;
     }
   }
@@ -621,30 +630,30 @@ inline dim3 grid_body(int n, int ncomp) {
   } while (0)
 
 template <int PREC>
-hipError_t launch_accel_p(const Plan &pl, int n, const double *pos,
-                          const double *mass, double eps2, double scale,
-                          double *out, size_t stride, hipStream_t st) {
+hipError_t launch_accel_p(const Plan &pl, int n, int row0, int nt,
+                          const double *pos, const double *mass, double eps2,
+                          double scale, double *out, size_t stride,
+                          hipStream_t st) {
   const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
   const int jc = int(pl.jchunk);
-#define NBODY_ACCEL_CALL(R_, L_)                                              \
-  accel_kernel<PREC, R_, L_><<<grid, kThreads, 0, st>>>(n, pos, mass, eps2,  \
-                                                        scale, jc, out, stride)
+#define NBODY_ACCEL_CALL(R_, L_)                                             \
+  accel_kernel<PREC, R_, L_><<<grid, kThreads, 0, st>>>(                    \
+      n, row0, nt, pos, mass, eps2, scale, jc, out, stride)
   NBODY_RL_SWITCH(pl.R, pl.L, NBODY_ACCEL_CALL);
 #undef NBODY_ACCEL_CALL
   return hipGetLastError();
 }
 
 template <int PREC>
-hipError_t launch_vjp_p(const Plan &pl, int n, const double *pos,
-                        const double *mass, const double *gacc, double eps2,
-                        double scale, double *ox, double *om, size_t stride,
-                        hipStream_t st) {
+hipError_t launch_vjp_p(const Plan &pl, int n, int row0, int nt,
+                        const double *pos, const double *mass,
+                        const double *gacc, double eps2, double scale,
+                        double *ox, double *om, size_t stride, hipStream_t st) {
   const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
   const int jc = int(pl.jchunk);
 #define NBODY_VJP_CALL(R_, L_)                                               \
-  vjp_kernel<PREC, R_, L_><<<grid, kThreads, 0, st>>>(n, pos, mass, gacc,    \
-                                                      eps2, scale, jc, ox,   \
-                                                      om, stride)
+  vjp_kernel<PREC, R_, L_><<<grid, kThreads, 0, st>>>(                      \
+      n, row0, nt, pos, mass, gacc, eps2, scale, jc, ox, om, stride)
   NBODY_RL_SWITCH(pl.R, pl.L, NBODY_VJP_CALL);
 #undef NBODY_VJP_CALL
   return hipGetLastError();
@@ -657,13 +666,18 @@ hipError_t launch_vjp_p(const Plan &pl, int n, const double *pos,
 // ------------------------------------------------------------ launch plans --
 
 Plan make_plan(KernelKind kind, int precision, int64_t n) {
+  return make_plan(kind, precision, n, n);
+}
+
+Plan make_plan(KernelKind kind, int precision, int64_t nt, int64_t n) {
   // Chosen from launch-shape sweeps on MI355X (all-pairs kernel plus split
   // reduction).  Targets per lane R: 2 for FP64, 1 for the FP32-pair modes
   // (their pair chain is latency-bound, so more resident waves beat more
   // independent chains per lane).  About 8192 workgroups (32 per CU: 8
   // resident waves per SIMD, several rounds of them), reached with the
   // smallest lanes-per-target L in {1, 4, 16} that needs at most 64 source
-  // splits, each at least one 256-body tile long.
+  // splits, each at least one 256-body tile long.  Target blocks count the
+  // nt target rows, source splits the n source bodies.
   const int R = (precision == NBODY_FP64 && kind != kPotential) ? 2 : 1;
   const int64_t target = 8192, max_sj = 64;
   const int64_t ntiles = (n + kThreads - 1) / kThreads;
@@ -672,48 +686,49 @@ Plan make_plan(KernelKind kind, int precision, int64_t n) {
     const int64_t per_block = int64_t(kThreads / L) * R;
     p.R = R;
     p.L = L;
-    p.n_ib = (n + per_block - 1) / per_block;
+    p.n_ib = (nt + per_block - 1) / per_block;
     p.sj = (target + p.n_ib - 1) / p.n_ib;
     if (p.sj <= std::min(max_sj, ntiles)) break;
   }
-  p.sj = std::max<int64_t>(1, std::min(p.sj, ntiles));
+  p.sj = std::max<int64_t>(1, std::min({p.sj, ntiles, max_sj}));
   const int64_t tiles_per_split = (ntiles + p.sj - 1) / p.sj;
   p.jchunk = tiles_per_split * kThreads;
   p.sj = (n + p.jchunk - 1) / p.jchunk;
   return p;
 }
 
-hipError_t launch_accel(const Plan &pl, int precision, int n, const double *pos,
-                        const double *mass, double eps2, double scale,
-                        double *out, size_t stride, hipStream_t st) {
+hipError_t launch_accel(const Plan &pl, int precision, int n, int row0, int nt,
+                        const double *pos, const double *mass, double eps2,
+                        double scale, double *out, size_t stride,
+                        hipStream_t st) {
   switch (precision) {
     case NBODY_FP64:
-      return launch_accel_p<NBODY_FP64>(pl, n, pos, mass, eps2, scale, out,
-                                        stride, st);
+      return launch_accel_p<NBODY_FP64>(pl, n, row0, nt, pos, mass, eps2,
+                                        scale, out, stride, st);
     case NBODY_MIXED:
-      return launch_accel_p<NBODY_MIXED>(pl, n, pos, mass, eps2, scale, out,
-                                         stride, st);
+      return launch_accel_p<NBODY_MIXED>(pl, n, row0, nt, pos, mass, eps2,
+                                         scale, out, stride, st);
     case NBODY_MIXED_D64:
-      return launch_accel_p<NBODY_MIXED_D64>(pl, n, pos, mass, eps2, scale,
-                                             out, stride, st);
+      return launch_accel_p<NBODY_MIXED_D64>(pl, n, row0, nt, pos, mass, eps2,
+                                             scale, out, stride, st);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_vjp(const Plan &pl, int precision, int n, const double *pos,
-                      const double *mass, const double *gacc, double eps2,
-                      double scale, double *ox, double *om, size_t stride,
-                      hipStream_t st) {
+hipError_t launch_vjp(const Plan &pl, int precision, int n, int row0, int nt,
+                      const double *pos, const double *mass, const double *gacc,
+                      double eps2, double scale, double *ox, double *om,
+                      size_t stride, hipStream_t st) {
   switch (precision) {
     case NBODY_FP64:
-      return launch_vjp_p<NBODY_FP64>(pl, n, pos, mass, gacc, eps2, scale, ox,
-                                      om, stride, st);
+      return launch_vjp_p<NBODY_FP64>(pl, n, row0, nt, pos, mass, gacc, eps2,
+                                      scale, ox, om, stride, st);
     case NBODY_MIXED:
-      return launch_vjp_p<NBODY_MIXED>(pl, n, pos, mass, gacc, eps2, scale, ox,
-                                       om, stride, st);
+      return launch_vjp_p<NBODY_MIXED>(pl, n, row0, nt, pos, mass, gacc, eps2,
+                                       scale, ox, om, stride, st);
     case NBODY_MIXED_D64:
-      return launch_vjp_p<NBODY_MIXED_D64>(pl, n, pos, mass, gacc, eps2, scale,
-                                           ox, om, stride, st);
+      return launch_vjp_p<NBODY_MIXED_D64>(pl, n, row0, nt, pos, mass, gacc,
+                                           eps2, scale, ox, om, stride, st);
   }
   return hipErrorInvalidValue;
 }

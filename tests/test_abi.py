@@ -194,3 +194,62 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "_LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         binding.load_library()
+
+
+# ------------------------------------------------------------- row ranges --
+
+def test_rows_workspace_matches_full_call(B):
+    # the plan for all n rows is the whole-system plan (same split count, so
+    # the same workspace and, on the GPU, bitwise the same result)
+    for prec in (0, 1, 2):
+        for n in (1, 255, 256, 1000, 3001, 16384, 65536, 262144, 1 << 20):
+            for op in (B.NBODY_OP_ACCEL, B.NBODY_OP_VJP):
+                assert (B.nbody_rows_workspace_bytes(op, n, n, prec)
+                        == B.nbody_workspace_bytes(op, n, 0, 1, prec)), (op, n, prec)
+
+
+def test_rows_workspace_bytes(B):
+    inv = ctypes.c_size_t(-1).value
+    for prec in (0, 1, 2):
+        assert B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 1000, 0, prec) == 0
+        for n, rows in ((262144, 32768), (262144, 1), (1 << 28, 1), (5000, 77)):
+            a = B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, n, rows, prec)
+            v = B.nbody_rows_workspace_bytes(B.NBODY_OP_VJP, n, rows, prec)
+            # at most 64 source splits of FP64 partials
+            assert a % 256 == 0 and a <= 64 * 3 * rows * 8 + 256
+            assert v % 256 == 0 and v <= 64 * 4 * rows * 8 + 256
+        assert B.nbody_rows_workspace_bytes(B.NBODY_OP_STEP, 1000, 10, prec) == inv
+        assert B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 1000, 1001, prec) == inv
+        assert B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 1000, -1, prec) == inv
+    assert B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 1000, 10, 3) == inv
+
+
+def test_rows_reject_invalid_ranges(B):
+    lib = B.load_library()
+
+    def acc_rows(n=1000, r0=0, rc=10, pos=FAKE, prec=0):
+        return lib.nbody_accel_rows(n, r0, rc, _p(pos), _p(FAKE), _p(FAKE),
+                                    _params(B), prec, _p(FAKE), 1 << 30, None)
+
+    def vjp_rows(n=1000, r0=0, rc=10, gacc=FAKE):
+        return lib.nbody_accel_vjp_rows(n, r0, rc, _p(FAKE), _p(FAKE), _p(gacc),
+                                        _p(FAKE), _p(FAKE), _params(B), 0,
+                                        _p(FAKE), 1 << 30, None)
+    for f in (acc_rows, vjp_rows):
+        assert f(r0=-1) == 1
+        assert f(rc=-1) == 1
+        assert f(r0=995, rc=6) == 1
+        assert "outside [0, n" in lib.nbody_last_error().decode()
+        assert f(r0=1001, rc=0) == 1
+        assert f(n=0) == 1
+        # an empty range is a valid no-op: pointers are not examined
+        assert f(r0=1000, rc=0) == 0
+    assert acc_rows(rc=0, pos=0) == 0
+    assert acc_rows(pos=0) == 1
+    assert acc_rows(prec=7) == 1
+    assert vjp_rows(gacc=0) == 1
+    # too small a workspace
+    need = B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 262144, 32768, 1)
+    assert need > 0
+    assert lib.nbody_accel_rows(262144, 0, 32768, _p(FAKE), _p(FAKE), _p(FAKE),
+                                _params(B), 1, _p(FAKE), need - 8, None) == 2
