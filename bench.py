@@ -53,7 +53,9 @@ FLOPS_PER_PAIR = {"accel": 20, "vjp": 48, "diag": 13}
 MEASURED_TRAFFIC = {("vjp", "mixed"): {"bytes": 24.2e6, "src_sha256": "84cc4c1565e625bd"}}
 KERNEL_SRC = os.path.join(ROOT, "paper_2203_08263_amd", "csrc", "nbody_kernels.hip")
 DTYPE = {"fp64": "f64", "mixed": "f32-pair/f64-acc",
-         "mixed_d64": "f32-pair(f64-diff)/f64-acc"}
+         "mixed_d64": "f32-pair(f64-diff)/f64-acc",
+         "mixed_nf": "f32-pair(near f64-diff, far recentred)/f64-acc"}
+PRECS = ("fp64", "mixed", "mixed_d64", "mixed_nf")
 
 
 def log(*a):
@@ -89,30 +91,44 @@ class Bench:
         self.GM = torch.empty_like(self.M)
         self.CK = torch.empty(B.nbody_checkpoint_bytes(n, w.steps, CKPT_EVERY) // 8,
                               dtype=torch.float64, device=dev)
+        # the near / far mode runs on the same bodies in Morton order (sorted
+        # once here on the GPU; perm maps its results back)
+        self.perm, self.P0s, self.V0s, self.Ms = B.nbody_morton_sort(self.P0, self.M,
+                                                                     self.V0)
+        self.GX0s = self.GX0[:, self.perm].contiguous()
         self.A0 = {}
         self.ws = {}
-        for p in ("fp64", "mixed", "mixed_d64"):
-            self.A0[p] = B.nbody_accel(self.P0, self.M, w.G, w.eps, p)
+        for p in PRECS:
+            P0, M = self.state0(p)[0], self.state0(p)[2]
+            self.A0[p] = B.nbody_accel(P0, M, w.G, w.eps, p)
             nb = max(B.nbody_workspace_bytes(B.NBODY_OP_STEP, n, w.steps, CKPT_EVERY, p),
                      B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, n, w.steps,
                                              CKPT_EVERY, p), 256)
             self.ws[p] = torch.empty(nb, dtype=torch.uint8, device=dev)
         torch.cuda.synchronize()
 
+    def state0(self, p):
+        """(x_0, v_0, m, dL/dx_S) in the body order precision p runs in."""
+        if p == "mixed_nf":
+            return self.P0s, self.V0s, self.Ms, self.GX0s
+        return self.P0, self.V0, self.M, self.GX0
+
     def forward(self, p):
         w, B = self.w, self.B
-        self.P.copy_(self.P0)
-        self.V.copy_(self.V0)
+        P0, V0, M, _ = self.state0(p)
+        self.P.copy_(P0)
+        self.V.copy_(V0)
         self.A.copy_(self.A0[p])
-        B.nbody_step(self.P, self.V, self.A, self.M, w.G, w.eps, w.dt, w.steps, p,
+        B.nbody_step(self.P, self.V, self.A, M, w.G, w.eps, w.dt, w.steps, p,
                      acc_valid=True, ckpt=self.CK, ckpt_every=CKPT_EVERY,
                      workspace=self.ws[p])
 
     def adjoint(self, p):
         w, B = self.w, self.B
-        self.GX.copy_(self.GX0)
+        _, _, M, GX0 = self.state0(p)
+        self.GX.copy_(GX0)
         self.GV.zero_()
-        B.nbody_step_adjoint(self.CK, self.M, self.GX, self.GV, w.G, w.eps, w.dt,
+        B.nbody_step_adjoint(self.CK, M, self.GX, self.GV, w.G, w.eps, w.dt,
                              w.steps, CKPT_EVERY, p, gmass=self.GM,
                              workspace=self.ws[p])
 
@@ -143,10 +159,11 @@ def roofline(bench, p, kind):
     against the vector peak of its arithmetic type."""
     torch, B, w = bench.torch, bench.B, bench.w
     n = w.n
+    P0, _, M, GX0 = bench.state0(p)
     if kind == "accel":
-        fn = lambda: B.nbody_accel(bench.P0, bench.M, w.G, w.eps, p, out=bench.A)  # noqa
+        fn = lambda: B.nbody_accel(P0, M, w.G, w.eps, p, out=bench.A)  # noqa
     else:
-        fn = lambda: B.nbody_accel_vjp(bench.P0, bench.M, bench.GX0, w.G, w.eps, p,  # noqa
+        fn = lambda: B.nbody_accel_vjp(P0, M, GX0, w.G, w.eps, p,  # noqa
                                        gpos=bench.GX, gmass=bench.GM)
     warm(bench.torch, fn)
     ms, _ = bench.timed(fn, reps=50, warmup=3)
@@ -180,23 +197,39 @@ def shape_legs(torch, B, inputs):
     dev = torch.device("cuda:0")
     T = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa
     out = {}
-    for name, precs, kinds in (("plummer65536", ("mixed", "mixed_d64", "fp64"),
+    for name, precs, kinds in (("plummer65536", ("mixed", "mixed_d64", "fp64", "mixed_nf"),
                                 ("accel", "diag")),
-                               ("plummer262144_vjp", ("mixed", "mixed_d64", "fp64"),
+                               ("plummer262144_vjp", ("mixed", "mixed_d64", "fp64",
+                                                      "mixed_nf"),
                                 ("accel", "vjp", "accel_share8", "vjp_share8"))):
         w = inputs.WORKLOADS[name]
         pos, vel, mass = w.initial_state()
-        P, M, Vt = T(pos), T(mass), T(vel)
+        P0, M0, V0 = T(pos), T(mass), T(vel)
         D = torch.empty(9, dtype=torch.float64, device=dev)
-        Gt = T(inputs.upstream_normal(w.n, w.seed + 400))
-        A, GX, GM = torch.empty_like(P), torch.empty_like(P), torch.empty_like(M)
+        G0 = T(inputs.upstream_normal(w.n, w.seed + 400))
+        # Morton order for the near / far mode; the sort itself is timed too
+        sort_fn = lambda: B.nbody_morton_sort(P0, M0, V0)  # noqa
+        warm(torch, sort_fn)
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record()
+        for _ in range(5):
+            perm, Ps, Vs, Ms = sort_fn()
+        s1.record()
+        torch.cuda.synchronize()
+        sort_ms = s0.elapsed_time(s1) / 5
+        Gs = G0[:, perm].contiguous()
+        A, GX, GM = torch.empty_like(P0), torch.empty_like(P0), torch.empty_like(M0)
         share = w.n // 8
         r0 = 3 * share
         As = torch.empty((3, share), dtype=torch.float64, device=dev)
         GXs = torch.empty((3, share), dtype=torch.float64, device=dev)
         GMs = torch.empty(share, dtype=torch.float64, device=dev)
-        res = {}
+        res = {"morton_sort_ms": round(sort_ms, 4)}
         for p in precs:
+            if p == "mixed_nf":
+                P, M, Vt, Gt = Ps, Ms, Vs, Gs
+            else:
+                P, M, Vt, Gt = P0, M0, V0, G0
             ws = torch.empty(max(B.nbody_workspace_bytes(B.NBODY_OP_ACCEL, w.n, 0, 1, p),
                                  B.nbody_workspace_bytes(B.NBODY_OP_VJP, w.n, 0, 1, p),
                                  B.nbody_workspace_bytes(B.NBODY_OP_DIAGNOSTICS, w.n, 0, 1,
@@ -240,6 +273,8 @@ def shape_legs(torch, B, inputs):
                     "frac_of_vector_peak": round(ips * fl / 1e12 / peak, 4)}
         if "vjp_mixed" in res:
             for p in precs:
+                if "vjp_%s" % p not in res:
+                    continue
                 res["vjp_over_fwd_%s" % p] = round(res["vjp_%s" % p]["ms"] /
                                                    res["accel_%s" % p]["ms"], 3)
         out[name] = res
@@ -327,8 +362,13 @@ def cpu_baseline(bench, p, gx_gpu, gv_gpu, gm_gpu, x_end, v_end):
     err["energy_drift_%s_%dsteps" % (p, w.steps)] = float("%.3e" % (abs(e1 - e0) / abs(e0)))
     rows = w.rows(2048)
     ref = oracle.accel_rows(pos, mass, w.G, w.eps, rows)
-    for q in ("fp64", "mixed", "mixed_d64"):
-        a = bench.A0[q].cpu().numpy()[:, rows]
+    for q in PRECS:
+        a = bench.A0[q].cpu().numpy()
+        if q == "mixed_nf":              # back from Morton order
+            back = np.empty_like(a)
+            back[:, bench.perm.cpu().numpy()] = a
+            a = back
+        a = a[:, rows]
         err["accel_x0_2048rows_%s" % q] = {k: float("%.3e" % v) for k, v in
                                           metrics.rel_errors(a, ref).items()}
     return base, err
@@ -339,8 +379,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="timed steps")
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--precision", default="mixed",
-                    choices=["fp64", "mixed", "mixed_d64"])
+    ap.add_argument("--precision", default="mixed", choices=PRECS)
     ap.add_argument("--no-legs", action="store_true",
                     help="time only the main precision's forward + adjoint")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -377,12 +416,13 @@ def main(argv=None):
         dst = torch.empty_like(src)
         dst.copy_(src)                       # calibration: 64 MiB read + write
         torch.cuda.synchronize()
+        P0, _, M, GX0 = bench.state0(p)
         for _ in range(args.steps):
             if args.profile == "accel":
-                B.nbody_accel(bench.P0, bench.M, w.G, w.eps, p, out=bench.A)
+                B.nbody_accel(P0, M, w.G, w.eps, p, out=bench.A)
             else:
-                B.nbody_accel_vjp(bench.P0, bench.M, bench.GX0, w.G, w.eps, p,
-                                  gpos=bench.GX, gmass=bench.GM)
+                B.nbody_accel_vjp(P0, M, GX0, w.G, w.eps, p, gpos=bench.GX,
+                                  gmass=bench.GM)
         torch.cuda.synchronize()
         log("bench: profile mode done (%s, %s, %d launches)" % (args.profile, p,
                                                                  args.steps))
@@ -402,7 +442,7 @@ def main(argv=None):
 
     legs = {}
     if not args.no_legs:
-        for q in ("fp64", "mixed", "mixed_d64"):
+        for q in PRECS:
             warm(torch, lambda: bench.forward(q))
             fms, _ = bench.timed(lambda: bench.forward(q), 10, 2)
             sms, _ = bench.timed(lambda: bench.step(q), 5, 1)

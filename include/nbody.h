@@ -67,11 +67,25 @@ typedef struct nbody_params {
  *                   32 sources are added into FP64 per-body accumulators.
  *  NBODY_MIXED_D64  as NBODY_MIXED, but the coordinate difference x_j - x_i
  *                   is taken in FP64 and rounded once to FP32, removing the
- *                   error of rounding each position to FP32 first. */
+ *                   error of rounding each position to FP32 first.
+ *  NBODY_MIXED_NF   near / far: for each run of sources one FP32 chunk sum
+ *                   covers and each wave of targets, a run whose bounding
+ *                   box is farther from the wave's targets' box than half the
+ *                   half-diagonal b of the workgroup's target box uses
+ *                   coordinates relative to that box's centre c (x - c in
+ *                   FP64, rounded once to FP32) with the NBODY_MIXED
+ *                   arithmetic; every other run uses the NBODY_MIXED_D64
+ *                   arithmetic.  Coordinate error per pair below
+ *                   6 u32 |x_j - x_i| (u32 = 2^-24).  Close to NBODY_MIXED
+ *                   speed when the bodies are in a spatial order
+ *                   (nbody_morton_sort); in a random order every run is near
+ *                   and results are bitwise those of NBODY_MIXED_D64.
+ *                   nbody_diagnostics evaluates W as NBODY_MIXED_D64. */
 enum nbody_precision {
   NBODY_FP64 = 0,
   NBODY_MIXED = 1,
-  NBODY_MIXED_D64 = 2
+  NBODY_MIXED_D64 = 2,
+  NBODY_MIXED_NF = 3
 };
 
 enum nbody_status {
@@ -100,7 +114,8 @@ enum nbody_op {
   NBODY_OP_STEP = 1,
   NBODY_OP_VJP = 2,
   NBODY_OP_STEP_ADJOINT = 3,
-  NBODY_OP_DIAGNOSTICS = 4
+  NBODY_OP_DIAGNOSTICS = 4,
+  NBODY_OP_MORTON_SORT = 5
 };
 
 /* Largest supported body count. */
@@ -259,6 +274,31 @@ int nbody_accel_vjp_rows(int64_t n, int64_t row_begin, int64_t row_count,
                          const double *gacc, double *gpos, double *gmass,
                          const nbody_params *p, int precision, void *ws,
                          size_t ws_bytes, void *stream);
+
+/* Spatial order for NBODY_MIXED_NF (the GPU counterpart of the paper's data
+ * locality concern, section 3.3: bodies that interact strongly sit in the
+ * same tiles).  Sorts the bodies by the Morton (Z-order) code of their
+ * positions on a 1024^3 grid spanning the cube [lo, lo + ext]^3 (lo the
+ * componentwise minimum, ext the largest extent of the bounding box):
+ *     q_c = min(1023, floor((x_c - lo_c) * (1024 / ext)))   (FP64)
+ * with the bits of q_x, q_y, q_z interleaved from the most significant
+ * down (x first); equal codes keep their original order (stable sort).
+ *  pos, mass [vector / scalar] in;  vel [vector] in, nullable
+ *  perm     [n int64] out  perm[r] = original index of sorted body r
+ *  pos_out, mass_out out   pos_out[:, r] = pos[:, perm[r]], likewise mass
+ *  vel_out  [vector] out   NULL exactly when vel is NULL
+ *  ws       >= nbody_workspace_bytes(NBODY_OP_MORTON_SORT, n, 0, 1, any
+ *              precision): tile boxes, the bounding box and 2^ceil(log2 n)
+ *              64-bit keys
+ * Outputs must not overlap the inputs.  Not on the per-step path: a rollout
+ * re-sorts as often as its bodies mix (every call permutes the state, so the
+ * caller keeps perm to map results back).
+ * Errors: INVALID_ARGUMENT (n, NULL or misaligned pointers, vel / vel_out
+ * not both NULL or both set), WORKSPACE_TOO_SMALL, HIP. */
+int nbody_morton_sort(int64_t n, const double *pos, const double *vel,
+                      const double *mass, int64_t *perm, double *pos_out,
+                      double *vel_out, double *mass_out, void *ws,
+                      size_t ws_bytes, void *stream);
 
 /* Static description of a status code (never NULL). */
 const char *nbody_error_string(int code);

@@ -20,8 +20,9 @@ _LIB_PATH = os.path.join(_HERE, "libnbody_hip.so")
 NBODY_FP64 = 0
 NBODY_MIXED = 1
 NBODY_MIXED_D64 = 2
+NBODY_MIXED_NF = 3
 PRECISIONS = {"fp64": NBODY_FP64, "mixed": NBODY_MIXED,
-              "mixed_d64": NBODY_MIXED_D64}
+              "mixed_d64": NBODY_MIXED_D64, "mixed_nf": NBODY_MIXED_NF}
 
 NBODY_OK = 0
 NBODY_ACC_VALID = 1
@@ -29,13 +30,14 @@ NBODY_HALF_KICK_DRIFT = 2
 INTEGRATORS = {"kdk": 0, "half_kick_drift": NBODY_HALF_KICK_DRIFT}
 NBODY_OP_ACCEL, NBODY_OP_STEP, NBODY_OP_VJP, NBODY_OP_STEP_ADJOINT = 0, 1, 2, 3
 NBODY_OP_DIAGNOSTICS = 4
+NBODY_OP_MORTON_SORT = 5
 NBODY_MAX_N = 1 << 28
 
 SYMBOLS = ("nbody_workspace_bytes", "nbody_checkpoint_bytes", "nbody_accel",
            "nbody_step", "nbody_accel_vjp", "nbody_step_adjoint",
            "nbody_diagnostics", "nbody_rows_workspace_bytes",
-           "nbody_accel_rows", "nbody_accel_vjp_rows", "nbody_error_string",
-           "nbody_last_error")
+           "nbody_accel_rows", "nbody_accel_vjp_rows", "nbody_morton_sort",
+           "nbody_error_string", "nbody_last_error")
 
 _INVALID = ctypes.c_size_t(-1).value
 
@@ -87,9 +89,10 @@ def load_library():
     lib.nbody_accel_rows.argtypes = [i64, i64, i64, vp, vp, vp, pp, ci, vp, sz, vp]
     lib.nbody_accel_vjp_rows.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, pp, ci,
                                          vp, sz, vp]
+    lib.nbody_morton_sort.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     for f in ("nbody_accel", "nbody_step", "nbody_accel_vjp",
               "nbody_step_adjoint", "nbody_diagnostics", "nbody_accel_rows",
-              "nbody_accel_vjp_rows"):
+              "nbody_accel_vjp_rows", "nbody_morton_sort"):
         getattr(lib, f).restype = ci
     lib.nbody_error_string.argtypes = [ci]
     lib.nbody_error_string.restype = ctypes.c_char_p
@@ -361,3 +364,26 @@ def nbody_accel_vjp_rows(pos, mass, gacc, row_begin, row_count, G=1.0, eps=1e-3,
                                     ctypes.byref(prm), prec, _ptr(ws), wsb,
                                     _stream(dev)))
     return gpos, gmass
+
+
+def nbody_morton_sort(pos, mass, vel=None, workspace=None):
+    """Bodies in Morton (Z) order of their positions: returns (perm, pos_out,
+    vel_out or None, mass_out) with pos_out[:, r] = pos[:, perm[r]]."""
+    lib = load_library()
+    n = mass.shape[0]
+    dev = mass.device
+    _scal(mass, n, "mass")
+    _vec(pos, n, "pos", dev)
+    if vel is not None:
+        _vec(vel, n, "vel", dev)
+    perm = torch.empty(n, dtype=torch.int64, device=dev)
+    pos_out = torch.empty((3, n), dtype=torch.float64, device=dev)
+    vel_out = None if vel is None else torch.empty((3, n), dtype=torch.float64,
+                                                   device=dev)
+    mass_out = torch.empty(n, dtype=torch.float64, device=dev)
+    ws, wsb = _workspace(lib.nbody_workspace_bytes(NBODY_OP_MORTON_SORT, n, 0, 1, 0),
+                         dev, workspace)
+    _check(lib.nbody_morton_sort(n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(perm),
+                                 _ptr(pos_out), _ptr(vel_out), _ptr(mass_out),
+                                 _ptr(ws), wsb, _stream(dev)))
+    return perm, pos_out, vel_out, mass_out

@@ -38,7 +38,8 @@ size_t round_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 size_t dbytes(int64_t count) { return round_up(size_t(count) * sizeof(double)); }
 
 bool valid_precision(int p) {
-  return p == NBODY_FP64 || p == NBODY_MIXED || p == NBODY_MIXED_D64;
+  return p == NBODY_FP64 || p == NBODY_MIXED || p == NBODY_MIXED_D64 ||
+         p == NBODY_MIXED_NF;
 }
 
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
@@ -81,18 +82,35 @@ int check_ws(void *ws, size_t ws_bytes, size_t need) {
   return NBODY_OK;
 }
 
+int64_t num_tiles(int64_t n) { return (n + nbody::kThreads - 1) / nbody::kThreads; }
+
+// Bounding-box scratch of an NBODY_MIXED_NF launch (nt targets, n sources);
+// it sits at the start of the workspace of every all-pairs operation, the
+// partial sums after it.
+size_t nf_bytes(nbody::KernelKind kind, int prec, int64_t n, int64_t nt) {
+  if (prec != NBODY_MIXED_NF) return 0;
+  const Plan pl = nbody::make_plan(kind, prec, nt, n);
+  return round_up(nbody::near_far_box_doubles(kind, pl.L, n, nt) * sizeof(double));
+}
+size_t box_bytes_fwd(int64_t n, int prec) { return nf_bytes(nbody::kAccel, prec, n, n); }
+size_t box_bytes_vjp(int64_t n, int prec) { return nf_bytes(nbody::kVjp, prec, n, n); }
+
 // Workspace sizes of each operation (see the layouts in the entry points).
 size_t ws_accel(int64_t n, int prec) {
   const Plan pl = nbody::make_plan(nbody::kAccel, prec, n);
-  return pl.sj > 1 ? dbytes(pl.sj * 3 * n) : 0;
+  return box_bytes_fwd(n, prec) + (pl.sj > 1 ? dbytes(pl.sj * 3 * n) : 0);
 }
 size_t ws_step(int64_t n, int prec) {
   const Plan pl = nbody::make_plan(nbody::kAccel, prec, n);
-  return dbytes(pl.sj * 3 * n);
+  return box_bytes_fwd(n, prec) + dbytes(pl.sj * 3 * n);
 }
 size_t ws_vjp(int64_t n, int prec) {
   const Plan pl = nbody::make_plan(nbody::kVjp, prec, n);
-  return pl.sj > 1 ? dbytes(pl.sj * 4 * n) : 0;
+  return box_bytes_vjp(n, prec) + (pl.sj > 1 ? dbytes(pl.sj * 4 * n) : 0);
+}
+size_t ws_morton(int64_t n) {
+  return dbytes(6 * num_tiles(n)) + dbytes(6) +
+         round_up(size_t(nbody::morton_padded(n)) * sizeof(uint64_t));
 }
 size_t ws_diag(int64_t n, int prec) {
   const Plan pl = nbody::make_plan(nbody::kPotential, prec, n);
@@ -101,12 +119,17 @@ size_t ws_diag(int64_t n, int prec) {
 size_t ws_accel_rows(int64_t n, int64_t nt, int prec) {
   if (nt == 0) return 0;
   const Plan pl = nbody::make_plan(nbody::kAccel, prec, nt, n);
-  return pl.sj > 1 ? dbytes(pl.sj * 3 * nt) : 0;
+  return nf_bytes(nbody::kAccel, prec, n, nt) +
+         (pl.sj > 1 ? dbytes(pl.sj * 3 * nt) : 0);
 }
 size_t ws_vjp_rows(int64_t n, int64_t nt, int prec) {
   if (nt == 0) return 0;
   const Plan pl = nbody::make_plan(nbody::kVjp, prec, nt, n);
-  return pl.sj > 1 ? dbytes(pl.sj * 4 * nt) : 0;
+  return nf_bytes(nbody::kVjp, prec, n, nt) +
+         (pl.sj > 1 ? dbytes(pl.sj * 4 * nt) : 0);
+}
+size_t box_bytes_adj(int64_t n, int prec) {
+  return std::max(box_bytes_fwd(n, prec), box_bytes_vjp(n, prec));
 }
 size_t ws_part_adjoint(int64_t n, int prec) {
   const Plan pf = nbody::make_plan(nbody::kAccel, prec, n);
@@ -115,8 +138,9 @@ size_t ws_part_adjoint(int64_t n, int prec) {
 }
 size_t ws_adjoint(int64_t n, int64_t steps, int64_t K, int prec) {
   const int64_t seg = std::min<int64_t>(K, std::max<int64_t>(steps, 1));
-  // v, a, abar, segment positions, partial sums
-  return 3 * dbytes(3 * n) + dbytes(seg * 3 * n) + ws_part_adjoint(n, prec);
+  // v, a, abar, segment positions, box scratch, partial sums
+  return 3 * dbytes(3 * n) + dbytes(seg * 3 * n) + box_bytes_adj(n, prec) +
+         ws_part_adjoint(n, prec);
 }
 
 int check_rows(int64_t n, int64_t row_begin, int64_t row_count) {
@@ -133,13 +157,37 @@ int64_t num_records(int64_t steps, int64_t K) {
   return std::max<int64_t>(1, (steps + K - 1) / K);
 }
 
+// The all-pairs launches (NBODY_MIXED_NF fills its box scratch first).
+hipError_t run_accel(const Plan &pl, int prec, int n, int r0, int nt,
+                     const double *pos, const double *mass, double *boxes,
+                     double eps2, double scale, double *out, size_t stride,
+                     hipStream_t st) {
+  return nbody::launch_accel(pl, prec, n, r0, nt, pos, mass, boxes, eps2,
+                             scale, out, stride, st);
+}
+
+hipError_t run_vjp(const Plan &pl, int prec, int n, int r0, int nt,
+                   const double *pos, const double *mass, const double *gacc,
+                   double *boxes, double eps2, double scale, double *ox,
+                   double *om, size_t stride, hipStream_t st) {
+  return nbody::launch_vjp(pl, prec, n, r0, nt, pos, mass, gacc, boxes, eps2,
+                           scale, ox, om, stride, st);
+}
+
+// Workspace carving: box scratch (NBODY_MIXED_NF only, box_bytes long) then
+// partial sums.
+double *ws_boxes(void *ws) { return static_cast<double *>(ws); }
+double *ws_parts(void *ws, size_t box_bytes) {
+  return reinterpret_cast<double *>(static_cast<char *>(ws) + box_bytes);
+}
+
 // One force evaluation into partial sums (unscaled; G is applied by the
 // consumer) -- the form the step loop and the recomputation share.
 int accel_to_parts(const Plan &pl, int prec, int n, const double *pos,
-                   const double *mass, double eps2, double *part,
-                   hipStream_t st) {
-  hipError_t e = nbody::launch_accel(pl, prec, n, 0, n, pos, mass, eps2, 1.0,
-                                     part, size_t(3) * n, st);
+                   const double *mass, double *boxes, double eps2,
+                   double *part, hipStream_t st) {
+  hipError_t e = run_accel(pl, prec, n, 0, n, pos, mass, boxes, eps2, 1.0,
+                           part, size_t(3) * n, st);
   return e == hipSuccess ? NBODY_OK : hip_fail(e, "accel kernel launch");
 }
 
@@ -171,6 +219,7 @@ size_t nbody_workspace_bytes(int op, int64_t n, int64_t steps,
       if (steps < 0 || ckpt_every < 1) return kInvalid;
       return ws_adjoint(n, steps, ckpt_every, precision);
     case NBODY_OP_DIAGNOSTICS: return ws_diag(n, precision);
+    case NBODY_OP_MORTON_SORT: return ws_morton(n);
   }
   return kInvalid;
 }
@@ -206,15 +255,17 @@ int nbody_accel(int64_t n, const double *pos, const double *mass, double *acc,
   const int nn = int(n);
   const double eps2 = p->eps * p->eps;
   const Plan pl = nbody::make_plan(nbody::kAccel, precision, n);
+  double *boxes = ws_boxes(ws);
   hipError_t e;
   if (pl.sj == 1) {
-    e = nbody::launch_accel(pl, precision, nn, 0, nn, pos, mass, eps2, p->G,
-                            acc, 0, st);
+    e = run_accel(pl, precision, nn, 0, nn, pos, mass, boxes, eps2, p->G, acc,
+                  0, st);
     if (e != hipSuccess) return hip_fail(e, "accel kernel launch");
     return NBODY_OK;
   }
-  double *part = static_cast<double *>(ws);
-  if ((rc = accel_to_parts(pl, precision, nn, pos, mass, eps2, part, st)))
+  double *part = ws_parts(ws, box_bytes_fwd(n, precision));
+  if ((rc = accel_to_parts(pl, precision, nn, pos, mass, boxes, eps2, part,
+                           st)))
     return rc;
   e = nbody::launch_reduce(nn, int(pl.sj), part, size_t(3) * n, p->G, acc,
                            nullptr, st);
@@ -238,15 +289,16 @@ int nbody_accel_rows(int64_t n, int64_t row_begin, int64_t row_count,
   const int nn = int(n), r0 = int(row_begin), nt = int(row_count);
   const double eps2 = p->eps * p->eps;
   const Plan pl = nbody::make_plan(nbody::kAccel, precision, row_count, n);
+  double *boxes = ws_boxes(ws);
   hipError_t e;
   if (pl.sj == 1) {
-    e = nbody::launch_accel(pl, precision, nn, r0, nt, pos, mass, eps2, p->G,
-                            acc, 0, st);
+    e = run_accel(pl, precision, nn, r0, nt, pos, mass, boxes, eps2, p->G, acc,
+                  0, st);
     return e == hipSuccess ? NBODY_OK : hip_fail(e, "accel kernel launch");
   }
-  double *part = static_cast<double *>(ws);
-  e = nbody::launch_accel(pl, precision, nn, r0, nt, pos, mass, eps2, 1.0,
-                          part, size_t(3) * nt, st);
+  double *part = ws_parts(ws, nf_bytes(nbody::kAccel, precision, n, row_count));
+  e = run_accel(pl, precision, nn, r0, nt, pos, mass, boxes, eps2, 1.0, part,
+                size_t(3) * nt, st);
   if (e != hipSuccess) return hip_fail(e, "accel kernel launch");
   e = nbody::launch_reduce(nt, int(pl.sj), part, size_t(3) * nt, p->G, acc,
                            nullptr, st);
@@ -272,16 +324,17 @@ int nbody_accel_vjp_rows(int64_t n, int64_t row_begin, int64_t row_count,
   const int nn = int(n), r0 = int(row_begin), nt = int(row_count);
   const double eps2 = p->eps * p->eps;
   const Plan pl = nbody::make_plan(nbody::kVjp, precision, row_count, n);
+  double *boxes = ws_boxes(ws);
   hipError_t e;
   if (pl.sj == 1) {
-    e = nbody::launch_vjp(pl, precision, nn, r0, nt, pos, mass, gacc, eps2,
-                          p->G, gpos, gmass, 0, st);
+    e = run_vjp(pl, precision, nn, r0, nt, pos, mass, gacc, boxes, eps2, p->G,
+                gpos, gmass, 0, st);
     return e == hipSuccess ? NBODY_OK : hip_fail(e, "vjp kernel launch");
   }
-  double *part = static_cast<double *>(ws);
+  double *part = ws_parts(ws, nf_bytes(nbody::kVjp, precision, n, row_count));
   const size_t stride = size_t(4) * nt;
-  e = nbody::launch_vjp(pl, precision, nn, r0, nt, pos, mass, gacc, eps2, 1.0,
-                        part, part + size_t(3) * nt, stride, st);
+  e = run_vjp(pl, precision, nn, r0, nt, pos, mass, gacc, boxes, eps2, 1.0,
+              part, part + size_t(3) * nt, stride, st);
   if (e != hipSuccess) return hip_fail(e, "vjp kernel launch");
   e = nbody::launch_reduce(nt, int(pl.sj), part, stride, p->G, gpos, gmass,
                            st);
@@ -316,7 +369,8 @@ int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
   const int nn = int(n);
   const double eps2 = p->eps * p->eps, G = p->G, dt = p->dt, h = 0.5 * dt;
   const Plan pl = nbody::make_plan(nbody::kAccel, precision, n);
-  double *part = static_cast<double *>(ws);
+  double *boxes = ws_boxes(ws);
+  double *part = ws_parts(ws, box_bytes_fwd(n, precision));
   const size_t stride = size_t(3) * n;
   const size_t rec_len = size_t(9) * n;
   hipError_t e;
@@ -327,7 +381,8 @@ int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
   const unsigned close_flag =
       (flags & NBODY_HALF_KICK_DRIFT) ? 0u : unsigned(nbody::kClose);
   if (!have_acc) {
-    if ((rc = accel_to_parts(pl, precision, nn, pos, mass, eps2, part, st)))
+    if ((rc = accel_to_parts(pl, precision, nn, pos, mass, boxes, eps2, part,
+                             st)))
       return rc;
   }
   if (!have_acc || ckpt || steps > 0) {
@@ -338,7 +393,8 @@ int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
     if (e != hipSuccess) return hip_fail(e, "update kernel launch");
   }
   for (int64_t t = 0; t < steps; ++t) {
-    if ((rc = accel_to_parts(pl, precision, nn, pos, mass, eps2, part, st)))
+    if ((rc = accel_to_parts(pl, precision, nn, pos, mass, boxes, eps2, part,
+                             st)))
       return rc;
     const bool more = t + 1 < steps;
     double *rec = nullptr;
@@ -367,16 +423,17 @@ int nbody_accel_vjp(int64_t n, const double *pos, const double *mass,
   const int nn = int(n);
   const double eps2 = p->eps * p->eps;
   const Plan pl = nbody::make_plan(nbody::kVjp, precision, n);
+  double *boxes = ws_boxes(ws);
   hipError_t e;
   if (pl.sj == 1) {
-    e = nbody::launch_vjp(pl, precision, nn, 0, nn, pos, mass, gacc, eps2, p->G,
-                          gpos, gmass, 0, st);
+    e = run_vjp(pl, precision, nn, 0, nn, pos, mass, gacc, boxes, eps2, p->G,
+                gpos, gmass, 0, st);
     return e == hipSuccess ? NBODY_OK : hip_fail(e, "vjp kernel launch");
   }
-  double *part = static_cast<double *>(ws);
+  double *part = ws_parts(ws, box_bytes_vjp(n, precision));
   const size_t stride = size_t(4) * n;
-  e = nbody::launch_vjp(pl, precision, nn, 0, nn, pos, mass, gacc, eps2, 1.0,
-                        part, part + size_t(3) * n, stride, st);
+  e = run_vjp(pl, precision, nn, 0, nn, pos, mass, gacc, boxes, eps2, 1.0, part,
+              part + size_t(3) * n, stride, st);
   if (e != hipSuccess) return hip_fail(e, "vjp kernel launch");
   e = nbody::launch_reduce(nn, int(pl.sj), part, stride, p->G, gpos, gmass, st);
   return e == hipSuccess ? NBODY_OK : hip_fail(e, "reduce kernel launch");
@@ -416,7 +473,8 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
   const size_t q3 = size_t(3) * n, rec_len = size_t(9) * n;
   const int64_t seg_max = std::min<int64_t>(ckpt_every,
                                             std::max<int64_t>(steps, 1));
-  // Workspace layout: v | a | abar | seg[seg_max] positions | partial sums.
+  // Workspace layout: v | a | abar | seg[seg_max] positions | tile boxes |
+  // partial sums.
   char *w = static_cast<char *>(ws);
   double *v_ws = reinterpret_cast<double *>(w);
   w += dbytes(3 * n);
@@ -426,6 +484,8 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
   w += dbytes(3 * n);
   double *seg = reinterpret_cast<double *>(w);
   w += dbytes(seg_max * 3 * n);
+  double *boxes = reinterpret_cast<double *>(w);
+  w += box_bytes_adj(n, precision);
   double *part = reinterpret_cast<double *>(w);
   hipError_t e;
 
@@ -448,7 +508,8 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
     if (e != hipSuccess) return hip_fail(e, "update kernel launch");
     for (int64_t t = 1; t < k; ++t) {
       const double *xp = seg + size_t(t - 1) * q3;
-      if ((rc = accel_to_parts(pf, precision, nn, xp, mass, eps2, part, st)))
+      if ((rc = accel_to_parts(pf, precision, nn, xp, mass, boxes, eps2, part,
+                               st)))
         return rc;
       e = nbody::launch_update(nn, int(pf.sj), part, q3, G, nullptr, a_ws, xp,
                                seg + size_t(t) * q3, v_ws, v_ws, h, dt,
@@ -461,8 +522,8 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
     // Reverse sweep over steps s0+k-1 .. s0: VJP at x_{t+1} = seg[t - s0].
     for (int64_t t = s0 + k - 1; t >= s0; --t) {
       const double *xt1 = seg + size_t(t - s0) * q3;
-      e = nbody::launch_vjp(pv, precision, nn, 0, nn, xt1, mass, abar, eps2,
-                            1.0, part, part + q3, size_t(4) * n, st);
+      e = run_vjp(pv, precision, nn, 0, nn, xt1, mass, abar, boxes, eps2, 1.0,
+                  part, part + q3, size_t(4) * n, st);
       if (e != hipSuccess) return hip_fail(e, "vjp kernel launch");
       // abar_t = (dt/2) vbar from the opening half-kick of step t, plus the
       // closing half-kick of step t-1 under kick-drift-kick.
@@ -475,8 +536,8 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
     }
   }
   // a_0 = A(x_0): final VJP at the initial positions (checkpoint record 0).
-  e = nbody::launch_vjp(pv, precision, nn, 0, nn, ckpt, mass, abar, eps2, 1.0,
-                        part, part + q3, size_t(4) * n, st);
+  e = run_vjp(pv, precision, nn, 0, nn, ckpt, mass, abar, boxes, eps2, 1.0,
+              part, part + q3, size_t(4) * n, st);
   if (e != hipSuccess) return hip_fail(e, "vjp kernel launch");
   e = nbody::launch_adj_combine(nn, int(pv.sj), part, size_t(4) * n, G, dt, h,
                                 gpos, gvel, gmass, abar, nbody::kAdjFinal, st);
@@ -506,6 +567,37 @@ int nbody_diagnostics(int64_t n, const double *pos, const double *vel,
   e = nbody::launch_diagnostics(precision, nn, int(pl.sj), phi, pos, vel, mass,
                                 eps2, p->G, blocksum, out, st);
   return e == hipSuccess ? NBODY_OK : hip_fail(e, "diagnostics launch");
+}
+
+int nbody_morton_sort(int64_t n, const double *pos, const double *vel,
+                      const double *mass, int64_t *perm, double *pos_out,
+                      double *vel_out, double *mass_out, void *ws,
+                      size_t ws_bytes, void *stream) {
+  int rc;
+  if (n < 1 || n > NBODY_MAX_N)
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "n = %lld outside [1, %lld]",
+                (long long)n, (long long)NBODY_MAX_N);
+  if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(mass, "mass")) ||
+      (rc = check_ptr(perm, "perm")) || (rc = check_ptr(pos_out, "pos_out")) ||
+      (rc = check_ptr(mass_out, "mass_out")))
+    return rc;
+  if ((vel == nullptr) != (vel_out == nullptr))
+    return fail(NBODY_ERR_INVALID_ARGUMENT,
+                "vel and vel_out must be both NULL or both set");
+  if (vel && ((rc = check_ptr(vel, "vel")) || (rc = check_ptr(vel_out, "vel_out"))))
+    return rc;
+  if ((rc = check_ws(ws, ws_bytes, ws_morton(n)))) return rc;
+  // Workspace layout: tile boxes | bounding box | keys.
+  char *w = static_cast<char *>(ws);
+  double *boxes = reinterpret_cast<double *>(w);
+  w += dbytes(6 * num_tiles(n));
+  double *gbox = reinterpret_cast<double *>(w);
+  w += dbytes(6);
+  uint64_t *keys = reinterpret_cast<uint64_t *>(w);
+  const hipError_t e = nbody::launch_morton_sort(
+      int(n), pos, vel, mass, perm, pos_out, vel_out, mass_out, boxes, gbox,
+      keys, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NBODY_OK : hip_fail(e, "morton sort launch");
 }
 
 }  // extern "C"

@@ -35,18 +35,33 @@ Plan make_plan(KernelKind kind, int precision, int64_t nt, int64_t n);
 // [3][n]), sources all n bodies; plan from make_plan(kind, precision, nt, n).
 // out + s*split_stride + c*nt + i  <-  scale * sum over source split s of the
 // acceleration sum of body row0 + i (without G when scale == 1), c = 0..2.
+// boxes: scratch of near_far_box_doubles(kAccel, pl.L, n, nt) doubles that
+// NBODY_MIXED_NF fills with bounding boxes before its kernel (NULL otherwise).
 hipError_t launch_accel(const Plan &pl, int precision, int n, int row0, int nt,
-                        const double *pos, const double *mass, double eps2,
-                        double scale, double *out, size_t split_stride,
-                        hipStream_t st);
+                        const double *pos, const double *mass, double *boxes,
+                        double eps2, double scale, double *out,
+                        size_t split_stride, hipStream_t st);
 
 // Rows as launch_accel, gacc [3][n]:
 // out_x + s*stride + c*nt + i <- scale * sum_j [s^-3/2 h - 3 s^-5/2 (e.h) e],
 // out_m + s*stride + i        <- -scale * sum_j (gbar_j . e) s^-3/2.
 hipError_t launch_vjp(const Plan &pl, int precision, int n, int row0, int nt,
                       const double *pos, const double *mass, const double *gacc,
-                      double eps2, double scale, double *out_x, double *out_m,
-                      size_t split_stride, hipStream_t st);
+                      double *boxes, double eps2, double scale, double *out_x,
+                      double *out_m, size_t split_stride, hipStream_t st);
+
+// Doubles of bounding-box scratch an NBODY_MIXED_NF launch of `kind` with
+// lanes-per-target L needs for nt targets against n sources.
+size_t near_far_box_doubles(KernelKind kind, int L, int64_t n, int64_t nt);
+
+// Morton (Z-order) sort: keys holds morton_padded(n) entries, boxes
+// ceil(n/256) * 6 doubles, gbox 6; vel / vel_out may both be NULL.
+int64_t morton_padded(int64_t n);
+hipError_t launch_morton_sort(int n, const double *pos, const double *vel,
+                              const double *mass, int64_t *perm,
+                              double *pos_out, double *vel_out,
+                              double *mass_out, double *boxes, double *gbox,
+                              uint64_t *keys, hipStream_t st);
 
 // out_x[c*n+i] = G * sum_s part[s*stride + c*n + i], c < 3; if out_m:
 // out_m[i] = G * sum_s part[s*stride + 3*n + i].  Fixed ascending s order.

@@ -5,7 +5,12 @@ w_ij = s_ij^-3/2, s_ij = |d_ij|^2 + eps^2 (d_ij = x_j - x_i):
 
 * rounding each position to FP32 (NBODY_MIXED) perturbs d_ij by
   delta_ij <= u32 (|x_i| + |x_j| + |d_ij|); the rounded FP64 difference
-  (NBODY_MIXED_D64) by delta_ij <= u32 |d_ij|; FP64 inputs are exact;
+  (NBODY_MIXED_D64) by delta_ij <= u32 |d_ij|; the near / far mode
+  (NBODY_MIXED_NF) by delta_ij <= u32 (|x_j - c| + |x_i - c| + |d_ij|) on
+  its far runs, where the workgroup target box's half-diagonal b bounds
+  |x_i - c| and every pair has |d_ij| > kappa b = b / 2, so
+  delta_ij < 6 u32 |d_ij|, and by u32 |d_ij| on its near runs (the D64
+  arithmetic); FP64 inputs are exact;
 * a perturbation delta of d changes f_ij by at most 4 G m_j w_ij delta
   (|d(d w)/dd| <= w (1 + 3 |d|^2 / s) <= 4 w);
 * the pair arithmetic (three FMAs for s, the hardware reciprocal square root
@@ -31,6 +36,24 @@ CHUNK32 = 32
 VJP_CHUNK32 = 16
 
 
+# Far runs of the near / far mode: a pair distance above kappa = 1/2 times
+# the target box's half-diagonal gives delta < (2 + 2 / kappa) u32 |d|.
+NF_DELTA = 6.0
+
+
+def _delta(precision, xn, blk, dn):
+    """Bound on the perturbation of the pair difference (rows blk, all j)."""
+    if precision == "mixed":
+        return U32 * (xn[blk, None] + xn[None, :] + dn)
+    if precision == "mixed_d64":
+        return U32 * dn
+    if precision == "mixed_nf":
+        return NF_DELTA * U32 * dn
+    if precision == "fp64":
+        return 0.0
+    raise ValueError(precision)
+
+
 def _rows_iter(rows, n):
     block = max(1, (1 << 22) // max(n, 1))
     for s in range(0, len(rows), block):
@@ -53,12 +76,7 @@ def accel_bound(pos, mass, G, eps, precision, rows=None):
         dn = np.sqrt((d * d).sum(axis=0))
         s = dn * dn + eps * eps
         w = mass[None, :] * s ** -1.5
-        if precision == "mixed":
-            delta = U32 * (xn[blk, None] + xn[None, :] + dn)
-        elif precision == "mixed_d64":
-            delta = U32 * dn
-        else:
-            delta = 0.0
+        delta = _delta(precision, xn, blk, dn)
         term = w * (4.0 * delta + (16 + L) * u * dn)
         term[np.arange(len(blk)), blk] = 0.0          # self pair: exactly 0
         out[k:k + len(blk)] = abs(G) * term.sum(axis=1)
@@ -97,12 +115,7 @@ def vjp_bound(pos, mass, gacc, G, eps, precision, rows=None):
         s = en * en + eps * eps
         y3 = s ** -1.5
         H = mass[blk, None] * gn[None, :] + mass[None, :] * gn[blk, None]
-        if precision == "mixed":
-            delta = U32 * (xn[blk, None] + xn[None, :] + en)
-        elif precision == "mixed_d64":
-            delta = U32 * en
-        else:
-            delta = 0.0
+        delta = _delta(precision, xn, blk, en)
         tx = y3 * H * (12.0 * delta / np.sqrt(s) + (40 + L) * u * 4.0)
         tm = y3 * gn[None, :] * (4.0 * delta + (16 + L) * u * en)
         # self pair: e = 0 and h = 0 exactly in the kernels

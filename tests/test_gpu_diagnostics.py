@@ -19,7 +19,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 U32, U64 = 2.0 ** -24, 2.0 ** -53
-PRECS = ["fp64", "mixed", "mixed_d64"]
+PRECS = ["fp64", "mixed", "mixed_d64", "mixed_nf"]
 
 
 def say(*a):
@@ -55,7 +55,7 @@ def potential_bound(pos, mass, G, eps, prec):
         y = s ** -0.5
         if prec == "mixed":
             delta = U32 * (xn[rows, None] + xn[None, :] + dn)
-        elif prec == "mixed_d64":
+        elif prec in ("mixed_d64", "mixed_nf"):   # the potential of NF is D64
             delta = U32 * dn
         else:
             delta = 0.0

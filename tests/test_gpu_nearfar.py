@@ -1,0 +1,193 @@
+"""GPU parity of the near / far precision mode (NBODY_MIXED_NF) and of the
+Morton sort it relies on for speed.
+
+* nbody_morton_sort: the permutation equals the oracle's NumPy Morton order
+  exactly (integer work, bit-exact), and the gathered state is an exact copy.
+* In a random body order every run of sources is near (its box spans the
+  system): NF equals NBODY_MIXED_D64 bitwise.
+* In Morton order (sorted by the oracle, so no input comes from the GPU
+  path) far tiles appear: NF differs from D64 and stays within its own
+  bound (coordinate error < 6 u32 |d| per pair) against the oracle, for the
+  acceleration, the VJP, row ranges, a rollout and its adjoint.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import _tol
+from paper_2203_08263_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_08263_amd import binding
+    binding.load_library()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def dev(B):
+    return torch.device("cuda:0")
+
+
+def T(a, dev):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def N(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _check_bound(got, ref, bound, what):
+    err = np.sqrt(((got - ref) ** 2).sum(axis=0))
+    worst = int(np.argmax(err / np.maximum(bound, 1e-300)))
+    assert np.all(err <= bound), "%s: row %d err %.3e bound %.3e" % (
+        what, worst, err[worst], bound[worst])
+    return err
+
+
+def _sorted_cube(oracle, n, seed):
+    pos, vel, mass = inputs.uniform_cube(n, seed)
+    o = oracle.morton_order(pos)
+    return pos[:, o].copy(), vel[:, o].copy(), mass[o].copy()
+
+
+# ------------------------------------------------------------ Morton sort --
+
+@pytest.mark.parametrize("n", [1, 2, 3, 1000, 2048, 2049, 70001])
+def test_morton_sort_matches_oracle(B, dev, oracle, n):
+    say("morton sort", n)
+    pos, vel, mass = inputs.uniform_cube(n, 1200 + n)
+    pos[2] *= 0.25                      # flat box: one cubic grid for all axes
+    perm, P, V, M = B.nbody_morton_sort(T(pos, dev), T(mass, dev), T(vel, dev))
+    want = oracle.morton_order(pos)
+    assert np.array_equal(N(perm), want)
+    assert np.array_equal(N(P), pos[:, want])
+    assert np.array_equal(N(V), vel[:, want])
+    assert np.array_equal(N(M), mass[want])
+
+
+def test_morton_sort_ties_plummer_and_no_velocity(B, dev, oracle):
+    # a clustered system with exact duplicates: equal codes keep index order
+    pos, _, mass = inputs.plummer(5000, 1301, a=0.1)
+    pos[:, 4000:] = pos[:, :1000]
+    perm, P, V, M = B.nbody_morton_sort(T(pos, dev), T(mass, dev))
+    assert V is None
+    want = oracle.morton_order(pos)
+    assert np.array_equal(N(perm), want)
+    assert np.array_equal(N(P), pos[:, want])
+
+
+# ------------------------------------------------------ near / far kernels --
+
+@pytest.mark.parametrize("n", [1, 300, 3001])
+def test_random_order_is_all_near_equals_d64(B, dev, n):
+    say("nf random order", n)
+    pos, _, mass = inputs.uniform_cube(n, 1400 + n)
+    g = inputs.upstream_normal(n, 1450 + n)
+    P, M, Gt = T(pos, dev), T(mass, dev), T(g, dev)
+    a_nf = N(B.nbody_accel(P, M, 1.0, 1e-3, "mixed_nf"))
+    a_d = N(B.nbody_accel(P, M, 1.0, 1e-3, "mixed_d64"))
+    assert np.array_equal(a_nf, a_d)
+    gx_nf, gm_nf = B.nbody_accel_vjp(P, M, Gt, 1.0, 1e-3, "mixed_nf")
+    gx_d, gm_d = B.nbody_accel_vjp(P, M, Gt, 1.0, 1e-3, "mixed_d64")
+    assert np.array_equal(N(gx_nf), N(gx_d))
+    assert np.array_equal(N(gm_nf), N(gm_d))
+
+
+@pytest.mark.parametrize("n", [2000, 16384])
+def test_sorted_accel_and_vjp_vs_oracle(B, dev, oracle, n):
+    say("nf sorted", n)
+    pos, _, mass = _sorted_cube(oracle, n, 1500 + n)
+    g = inputs.upstream_normal(n, 1550 + n)
+    P, M, Gt = T(pos, dev), T(mass, dev), T(g, dev)
+    a_nf = N(B.nbody_accel(P, M, 1.0, 1e-3, "mixed_nf"))
+    a_d = N(B.nbody_accel(P, M, 1.0, 1e-3, "mixed_d64"))
+    assert not np.array_equal(a_nf, a_d)        # far tiles were taken
+    rows = np.arange(n) if n <= 4096 else inputs.subset_rows(n, 1024, 1600)
+    ra = oracle.accel_rows(pos, mass, 1.0, 1e-3, rows)
+    err = _check_bound(a_nf[:, rows], ra,
+                       _tol.accel_bound(pos, mass, 1.0, 1e-3, "mixed_nf", rows), "accel")
+    rel = err / np.linalg.norm(ra, axis=0)
+    say("  accel E_max %.2e E_med %.2e" % (rel.max(), np.median(rel)))
+    gx, gm = B.nbody_accel_vjp(P, M, Gt, 1.0, 1e-3, "mixed_nf")
+    gx, gm = N(gx)[:, rows], N(gm)[rows]
+    rx, rm = oracle.accel_vjp_rows(pos, mass, g, 1.0, 1e-3, rows)
+    bx, bm = _tol.vjp_bound(pos, mass, g, 1.0, 1e-3, "mixed_nf", rows)
+    _check_bound(gx, rx, bx, "dL/dx")
+    assert np.all(np.abs(gm - rm) <= bm), "dL/dm"
+
+
+def test_sorted_rows_and_determinism(B, dev, oracle):
+    n = 5000
+    pos, _, mass = _sorted_cube(oracle, n, 1700)
+    P, M = T(pos, dev), T(mass, dev)
+    a1 = N(B.nbody_accel(P, M, 1.0, 1e-3, "mixed_nf"))
+    a2 = N(B.nbody_accel(P, M, 1.0, 1e-3, "mixed_nf"))
+    assert np.array_equal(a1, a2)
+    assert np.array_equal(a1, N(B.nbody_accel_rows(P, M, 0, n, 1.0, 1e-3, "mixed_nf")))
+    r0, rc = 1234, 999
+    rows = np.arange(r0, r0 + rc)
+    a = N(B.nbody_accel_rows(P, M, r0, rc, 1.0, 1e-3, "mixed_nf"))
+    _check_bound(a, oracle.accel_rows(pos, mass, 1.0, 1e-3, rows),
+                 _tol.accel_bound(pos, mass, 1.0, 1e-3, "mixed_nf", rows), "rows")
+
+
+def test_sorted_rollout_and_adjoint_vs_oracle(B, dev, oracle):
+    n, S, K = 2048, 6, 4
+    say("nf rollout + adjoint", n)
+    pos, vel, mass = _sorted_cube(oracle, n, 1800)
+    gxT = inputs.upstream_normal(n, 1801)
+    gvT = inputs.upstream_normal(n, 1802)
+    P, V, M = T(pos, dev), T(vel, dev), T(mass, dev)
+    A = torch.empty_like(P)
+    ck = torch.empty(B.nbody_checkpoint_bytes(n, S, K) // 8, dtype=torch.float64,
+                     device=dev)
+    B.nbody_step(P, V, A, M, 1.0, 1e-3, 1e-3, S, "mixed_nf", ckpt=ck, ckpt_every=K)
+    x_ref, v_ref, _ = oracle.step(pos, vel, mass, 1.0, 1e-3, 1e-3, S)
+    dx = np.linalg.norm(N(P) - x_ref) / np.linalg.norm(x_ref)
+    dv = np.linalg.norm(N(V) - v_ref) / np.linalg.norm(v_ref)
+    say("  state rel err x %.2e v %.2e" % (dx, dv))
+    assert dx < 1e-9 and dv < 1e-5
+    gx, gv = T(gxT, dev), T(gvT, dev)
+    gx, gv, gm = B.nbody_step_adjoint(ck, M, gx, gv, 1.0, 1e-3, 1e-3, S, K, "mixed_nf")
+    ox, ov, om = oracle.step_adjoint(pos, vel, mass, 1.0, 1e-3, 1e-3, S, gxT, gvT)
+    bx, bv, bm = _tol.adjoint_bound(oracle, pos, vel, mass, 1.0, 1e-3, 1e-3, S,
+                                    gxT, gvT, None, "mixed_nf")
+    _check_bound(N(gx), ox, bx, "dL/dx0")
+    _check_bound(N(gv), ov, bv, "dL/dv0")
+    assert np.all(np.abs(N(gm) - om) <= bm), "dL/dm"
+
+
+def test_plummer262144_sorted_share(B, dev, oracle):
+    # the clustered Plummer system in Morton order: accel and VJP on sampled
+    # rows of the whole system against the oracle
+    w = inputs.WORKLOADS["plummer262144_vjp"]
+    say("nf", w.name)
+    pos, _, mass = w.initial_state()
+    o = oracle.morton_order(pos)
+    pos, mass = pos[:, o].copy(), mass[o].copy()
+    g = inputs.upstream_normal(w.n, w.seed + 400)
+    P, M, Gt = T(pos, dev), T(mass, dev), T(g, dev)
+    rows = w.rows(256)
+    a = N(B.nbody_accel(P, M, w.G, w.eps, "mixed_nf"))[:, rows]
+    _check_bound(a, oracle.accel_rows(pos, mass, w.G, w.eps, rows),
+                 _tol.accel_bound(pos, mass, w.G, w.eps, "mixed_nf", rows), "accel")
+    gx, gm = B.nbody_accel_vjp(P, M, Gt, w.G, w.eps, "mixed_nf")
+    gx, gm = N(gx)[:, rows], N(gm)[rows]
+    rx, rm = oracle.accel_vjp_rows(pos, mass, g, w.G, w.eps, rows)
+    bx, bm = _tol.vjp_bound(pos, mass, g, w.G, w.eps, "mixed_nf", rows)
+    _check_bound(gx, rx, bx, "dL/dx")
+    assert np.all(np.abs(gm - rm) <= bm), "dL/dm"

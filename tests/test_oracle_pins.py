@@ -472,3 +472,58 @@ def test_half_kick_drift_adjoint_central_fd(oracle):
                                rtol=1e-6, atol=1e-7)
     np.testing.assert_allclose(gm, _central_fd(lambda z: loss(pos, vel, z), mass, h),
                                rtol=1e-6, atol=1e-7)
+
+
+# ------------------------------------------------------------ Morton order --
+
+def _morton_code_by_strings(q):
+    # bit interleaving written as string manipulation: the binary digits of
+    # q_x, q_y, q_z (10 each, most significant first) taken in turn
+    sx, sy, sz = (format(int(v), "010b") for v in q)
+    return int("".join(a + b + c for a, b, c in zip(sx, sy, sz)), 2)
+
+
+def test_morton_order_vs_string_interleaving(oracle):
+    rng = _rng(31)
+    pos = rng.uniform(-3.0, 5.0, size=(3, 400))
+    pos[1] *= 0.5            # anisotropic box: one cube of side ext for all axes
+    lo = pos.min(axis=1)
+    ext = max(pos.max(axis=1) - lo)
+    codes = []
+    for i in range(pos.shape[1]):
+        q = [min(1023, max(0, math.floor((pos[c, i] - lo[c]) * (1024.0 / ext))))
+             for c in range(3)]
+        codes.append(_morton_code_by_strings(q))
+    want = sorted(range(pos.shape[1]), key=lambda i: (codes[i], i))
+    assert list(oracle.morton_order(pos)) == want
+
+
+def test_morton_order_cube_corners(oracle):
+    # corners of a cube quantise to 0 or 1023 on every axis, so the code is
+    # 4x + 2y + z times 0b001001...001: lexicographic (x, y, z) order
+    corners = np.array([[x, y, z] for x in (0, 1) for y in (0, 1) for z in (0, 1)],
+                       dtype=float).T
+    shuffle = np.array([5, 2, 7, 0, 3, 6, 1, 4])
+    order = oracle.morton_order(corners[:, shuffle])
+    assert list(shuffle[order]) == list(range(8))
+
+
+def test_morton_order_z_curve_on_a_grid(oracle):
+    # 4 x 4 x 1 grid in the z = 0 plane, spanning [0, 3]^2: cells q = 341 * k
+    # (k = 0..3) have bits 0101..., and the curve visits the four 2 x 2
+    # quadrants in Z order, each quadrant itself in Z order
+    xs, ys = np.meshgrid(np.arange(4.0), np.arange(4.0), indexing="ij")
+    pos = np.stack([xs.ravel(), ys.ravel(), np.zeros(16)])
+    order = oracle.morton_order(pos)
+    visit = [(int(pos[0, i]), int(pos[1, i])) for i in order]
+    assert visit[:4] == [(0, 0), (0, 1), (1, 0), (1, 1)]
+    assert visit[4:8] == [(0, 2), (0, 3), (1, 2), (1, 3)]
+    assert visit[8:12] == [(2, 0), (2, 1), (3, 0), (3, 1)]
+    assert visit[12:] == [(2, 2), (2, 3), (3, 2), (3, 3)]
+
+
+def test_morton_order_ties_and_degenerate_box(oracle):
+    pos = np.zeros((3, 5))
+    assert list(oracle.morton_order(pos)) == [0, 1, 2, 3, 4]     # ext = 0
+    pos = np.array([[1.0, 0.0, 1.0, 0.0], [0.0] * 4, [0.0] * 4])
+    assert list(oracle.morton_order(pos)) == [1, 3, 0, 2]        # stable ties
