@@ -96,6 +96,13 @@ class Bench:
         self.perm, self.P0s, self.V0s, self.Ms = B.nbody_morton_sort(self.P0, self.M,
                                                                      self.V0)
         self.GX0s = self.GX0[:, self.perm].contiguous()
+        # the paper's single-precision variant: FP32 copies of the state
+        self.P0f, self.V0f, self.Mf = (t.float() for t in (self.P0, self.V0, self.M))
+        self.Pf, self.Vf = torch.empty_like(self.P0f), torch.empty_like(self.V0f)
+        self.Af0 = B.nbody_accel_f32(self.P0f, self.Mf, w.G, w.eps)
+        self.Af = torch.empty_like(self.Af0)
+        self.wsf = torch.empty(max(B.nbody_f32_workspace_bytes(B.NBODY_OP_STEP, n), 256),
+                               dtype=torch.uint8, device=dev)
         self.A0 = {}
         self.ws = {}
         for p in PRECS:
@@ -122,6 +129,14 @@ class Bench:
         B.nbody_step(self.P, self.V, self.A, M, w.G, w.eps, w.dt, w.steps, p,
                      acc_valid=True, ckpt=self.CK, ckpt_every=CKPT_EVERY,
                      workspace=self.ws[p])
+
+    def forward_f32(self):
+        w, B = self.w, self.B
+        self.Pf.copy_(self.P0f)
+        self.Vf.copy_(self.V0f)
+        self.Af.copy_(self.Af0)
+        B.nbody_step_f32(self.Pf, self.Vf, self.Af, self.Mf, w.G, w.eps, w.dt, w.steps,
+                         acc_valid=True, workspace=self.wsf)
 
     def adjoint(self, p):
         w, B = self.w, self.B
@@ -225,6 +240,26 @@ def shape_legs(torch, B, inputs):
         GXs = torch.empty((3, share), dtype=torch.float64, device=dev)
         GMs = torch.empty(share, dtype=torch.float64, device=dev)
         res = {"morton_sort_ms": round(sort_ms, 4)}
+        # FP32 state (the paper's single-precision variant): forward only
+        Pf, Mf = P0.float(), M0.float()
+        Af = torch.empty_like(Pf)
+        wsf = torch.empty(max(B.nbody_f32_workspace_bytes(B.NBODY_OP_ACCEL, w.n), 256),
+                          dtype=torch.uint8, device=dev)
+        fnf = lambda: B.nbody_accel_f32(Pf, Mf, w.G, w.eps, out=Af, workspace=wsf)  # noqa
+        warm(torch, fnf)
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20 if w.n <= 65536 else 4
+        f0.record()
+        for _ in range(reps):
+            fnf()
+        f1.record()
+        torch.cuda.synchronize()
+        fms = f0.elapsed_time(f1) / reps
+        fips = float(w.n) * w.n / (fms * 1e-3)
+        res["accel_f32_state"] = {
+            "ms": round(fms, 4), "G_int_s": round(fips / 1e9, 1),
+            "TFLOP_s": round(fips * 20 / 1e12, 2),
+            "frac_of_vector_peak": round(fips * 20 / 1e12 / PEAK_FP32_TFLOPS, 4)}
         for p in precs:
             if p == "mixed_nf":
                 P, M, Vt, Gt = Ps, Ms, Vs, Gs
@@ -452,6 +487,12 @@ def main(argv=None):
                        "fwd_adj_ms": round(sms, 4),
                        "bwd_over_fwd": round((sms - fms) / fms, 3)}
             log("bench: leg %s %s" % (q, legs[q]))
+        # FP32 state (forward only: this variant has no adjoint)
+        warm(torch, bench.forward_f32)
+        fms, _ = bench.timed(bench.forward_f32, 10, 2)
+        legs["f32_state"] = {"fwd_G_int_s": round(n2s / (fms * 1e-3) / 1e9, 1),
+                             "fwd_ms": round(fms, 4)}
+        log("bench: leg f32_state %s" % legs["f32_state"])
 
     # roofline of the dominant kernel of the step (the VJP: 11 launches of
     # ~2x the cost of each of the 18 force evaluations), plus the forward's

@@ -300,6 +300,39 @@ int nbody_morton_sort(int64_t n, const double *pos, const double *vel,
                       double *vel_out, double *mass_out, void *ws,
                       size_t ws_bytes, void *stream);
 
+/* Single-precision state: the paper's float32 variant (its FP32 runs of the
+ * section 3 listings; section 4 reports them next to FP64).  Positions,
+ * velocities, masses and accelerations are FP32 arrays ("f32 vector" = 3*n
+ * floats, component-major; "f32 scalar" = n floats, 4-byte aligned) and
+ * every operation is FP32, including the sum over sources (no FP64
+ * accumulation: results carry FP32 summation error over n terms).  Same
+ * launch plan, determinism and error rules as the FP64-state calls; there is
+ * no VJP / adjoint for this state type.
+ *
+ * Workspace bytes for op NBODY_OP_ACCEL or NBODY_OP_STEP; (size_t)-1 for any
+ * other op or invalid n. */
+size_t nbody_f32_workspace_bytes(int op, int64_t n);
+
+/* a_i = G sum_j m_j (x_j - x_i) (|x_j - x_i|^2 + eps^2)^(-3/2), all in FP32.
+ *  pos  [f32 vector] in;  mass [f32 scalar] in;  acc [f32 vector] out
+ *  p    host: G, eps as nbody_accel; G and eps^2 must also be finite and
+ *       eps^2 nonzero in FP32
+ * Errors: as nbody_accel. */
+int nbody_accel_f32(int64_t n, const float *pos, const float *mass, float *acc,
+                    const nbody_params *p, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* `steps` steps in place, all in FP32: kick-drift-kick, or the paper's
+ * half-kick + drift with NBODY_HALF_KICK_DRIFT (as nbody_step).
+ *  pos, vel [f32 vector] in/out;  acc [f32 vector] in (NBODY_ACC_VALID) /
+ *  out A(x_steps);  mass [f32 scalar] in
+ *  flags 0, NBODY_ACC_VALID, NBODY_HALF_KICK_DRIFT or both; no checkpoints
+ *  ws >= nbody_f32_workspace_bytes(NBODY_OP_STEP, n)
+ * Chaining is bitwise as for nbody_step.  Errors: as nbody_step. */
+int nbody_step_f32(int64_t n, int64_t steps, float *pos, float *vel,
+                   float *acc, const float *mass, const nbody_params *p,
+                   unsigned flags, void *ws, size_t ws_bytes, void *stream);
+
 /* Static description of a status code (never NULL). */
 const char *nbody_error_string(int code);
 

@@ -13,7 +13,8 @@ import importlib
 
 _BINDING = (
     "NBODY_FP64", "NBODY_MIXED", "NBODY_MIXED_D64", "NBODY_MIXED_NF", "PRECISIONS",
-    "NBodyError", "nbody_morton_sort",
+    "NBodyError", "nbody_morton_sort", "nbody_accel_f32", "nbody_step_f32",
+    "nbody_f32_workspace_bytes",
     "nbody_accel", "nbody_accel_vjp", "nbody_step", "nbody_step_adjoint",
     "nbody_diagnostics", "nbody_accel_rows", "nbody_accel_vjp_rows",
     "nbody_workspace_bytes", "nbody_rows_workspace_bytes",

@@ -37,6 +37,7 @@ SYMBOLS = ("nbody_workspace_bytes", "nbody_checkpoint_bytes", "nbody_accel",
            "nbody_step", "nbody_accel_vjp", "nbody_step_adjoint",
            "nbody_diagnostics", "nbody_rows_workspace_bytes",
            "nbody_accel_rows", "nbody_accel_vjp_rows", "nbody_morton_sort",
+           "nbody_f32_workspace_bytes", "nbody_accel_f32", "nbody_step_f32",
            "nbody_error_string", "nbody_last_error")
 
 _INVALID = ctypes.c_size_t(-1).value
@@ -90,9 +91,15 @@ def load_library():
     lib.nbody_accel_vjp_rows.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, pp, ci,
                                          vp, sz, vp]
     lib.nbody_morton_sort.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.nbody_f32_workspace_bytes.argtypes = [ci, i64]
+    lib.nbody_f32_workspace_bytes.restype = sz
+    lib.nbody_accel_f32.argtypes = [i64, vp, vp, vp, pp, vp, sz, vp]
+    lib.nbody_step_f32.argtypes = [i64, i64, vp, vp, vp, vp, pp, ctypes.c_uint, vp,
+                                   sz, vp]
     for f in ("nbody_accel", "nbody_step", "nbody_accel_vjp",
               "nbody_step_adjoint", "nbody_diagnostics", "nbody_accel_rows",
-              "nbody_accel_vjp_rows", "nbody_morton_sort"):
+              "nbody_accel_vjp_rows", "nbody_morton_sort", "nbody_accel_f32",
+              "nbody_step_f32"):
         getattr(lib, f).restype = ci
     lib.nbody_error_string.argtypes = [ci]
     lib.nbody_error_string.restype = ctypes.c_char_p
@@ -123,6 +130,17 @@ def _vec(t, n, name, device=None):
     if t.dtype != torch.float64 or t.shape != (3, n) or not t.is_contiguous():
         raise ValueError("%s must be a contiguous float64 (3, %d) tensor, got "
                          "%s %s" % (name, n, t.dtype, tuple(t.shape)))
+    if t.device.type != "cuda" or (device is not None and t.device != device):
+        raise ValueError("%s must be on the GPU device %s" % (name, device))
+    return t
+
+
+def _f32(t, shape, name, device=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != torch.float32 or tuple(t.shape) != shape or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous float32 %s tensor, got %s %s"
+                         % (name, shape, t.dtype, tuple(t.shape)))
     if t.device.type != "cuda" or (device is not None and t.device != device):
         raise ValueError("%s must be on the GPU device %s" % (name, device))
     return t
@@ -387,3 +405,43 @@ def nbody_morton_sort(pos, mass, vel=None, workspace=None):
                                  _ptr(pos_out), _ptr(vel_out), _ptr(mass_out),
                                  _ptr(ws), wsb, _stream(dev)))
     return perm, pos_out, vel_out, mass_out
+
+
+def nbody_f32_workspace_bytes(op: int, n: int) -> int:
+    return int(load_library().nbody_f32_workspace_bytes(op, n))
+
+
+def nbody_accel_f32(pos, mass, G=1.0, eps=1e-3, out=None, workspace=None):
+    """Accelerations (3, n) float32 of float32 state, all arithmetic FP32."""
+    lib = load_library()
+    n = mass.shape[0]
+    dev = mass.device
+    _f32(mass, (n,), "mass")
+    _f32(pos, (3, n), "pos", dev)
+    acc = torch.empty((3, n), dtype=torch.float32, device=dev) if out is None \
+        else _f32(out, (3, n), "out", dev)
+    ws, wsb = _workspace(lib.nbody_f32_workspace_bytes(NBODY_OP_ACCEL, n), dev,
+                         workspace)
+    prm = _Params(G, eps, 0.0)
+    _check(lib.nbody_accel_f32(n, _ptr(pos), _ptr(mass), _ptr(acc),
+                               ctypes.byref(prm), _ptr(ws), wsb, _stream(dev)))
+    return acc
+
+
+def nbody_step_f32(pos, vel, acc, mass, G=1.0, eps=1e-3, dt=1e-3, steps=1,
+                   acc_valid=False, workspace=None, integrator="kdk"):
+    """`steps` FP32 time steps in place on float32 pos, vel, acc."""
+    lib = load_library()
+    n = mass.shape[0]
+    dev = mass.device
+    _f32(mass, (n,), "mass")
+    for t, name in ((pos, "pos"), (vel, "vel"), (acc, "acc")):
+        _f32(t, (3, n), name, dev)
+    ws, wsb = _workspace(lib.nbody_f32_workspace_bytes(NBODY_OP_STEP, n), dev,
+                         workspace)
+    prm = _Params(G, eps, dt)
+    flags = (NBODY_ACC_VALID if acc_valid else 0) | _integrator(integrator)
+    _check(lib.nbody_step_f32(n, int(steps), _ptr(pos), _ptr(vel), _ptr(acc),
+                              _ptr(mass), ctypes.byref(prm), flags, _ptr(ws), wsb,
+                              _stream(dev)))
+    return pos, vel, acc

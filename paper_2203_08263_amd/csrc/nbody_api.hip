@@ -153,6 +153,40 @@ int check_rows(int64_t n, int64_t row_begin, int64_t row_count) {
   return NBODY_OK;
 }
 
+// ---- FP32 state
+size_t fbytes(int64_t count) { return round_up(size_t(count) * sizeof(float)); }
+
+Plan plan_f32(int64_t n) { return nbody::make_plan(nbody::kAccel, NBODY_MIXED, n); }
+
+size_t ws_accel_f32(int64_t n) {
+  const Plan pl = plan_f32(n);
+  return pl.sj > 1 ? fbytes(pl.sj * 3 * n) : 0;
+}
+size_t ws_step_f32(int64_t n) { return fbytes(plan_f32(n).sj * 3 * n); }
+
+bool aligned4(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+int check_fptr(const void *ptr, const char *name) {
+  if (!ptr) return fail(NBODY_ERR_INVALID_ARGUMENT, "%s is NULL", name);
+  if (!aligned4(ptr))
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "%s is not 4-byte aligned", name);
+  return NBODY_OK;
+}
+
+// The FP64-state checks, plus what FP32 arithmetic needs: G, eps^2 (and dt)
+// finite in FP32 and eps^2 not flushed to zero.
+int check_f32(int64_t n, const nbody_params *p, bool need_dt) {
+  int rc;
+  if ((rc = check_common(n, p, NBODY_MIXED, need_dt))) return rc;
+  const float G = float(p->G), e2 = float(p->eps * p->eps);
+  if (!isfinite(G)) return fail(NBODY_ERR_INVALID_ARGUMENT, "G overflows FP32");
+  if (!(e2 > 0.0f) || !isfinite(e2))
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "eps^2 is not a positive FP32 value");
+  if (need_dt && !isfinite(float(p->dt)))
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "dt overflows FP32");
+  return NBODY_OK;
+}
+
 int64_t num_records(int64_t steps, int64_t K) {
   return std::max<int64_t>(1, (steps + K - 1) / K);
 }
@@ -598,6 +632,91 @@ int nbody_morton_sort(int64_t n, const double *pos, const double *vel,
       int(n), pos, vel, mass, perm, pos_out, vel_out, mass_out, boxes, gbox,
       keys, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? NBODY_OK : hip_fail(e, "morton sort launch");
+}
+
+size_t nbody_f32_workspace_bytes(int op, int64_t n) {
+  if (n < 1 || n > NBODY_MAX_N) return kInvalid;
+  switch (op) {
+    case NBODY_OP_ACCEL: return ws_accel_f32(n);
+    case NBODY_OP_STEP: return ws_step_f32(n);
+  }
+  return kInvalid;
+}
+
+int nbody_accel_f32(int64_t n, const float *pos, const float *mass, float *acc,
+                    const nbody_params *p, void *ws, size_t ws_bytes,
+                    void *stream) {
+  int rc;
+  if ((rc = check_f32(n, p, false))) return rc;
+  if ((rc = check_fptr(pos, "pos")) || (rc = check_fptr(mass, "mass")) ||
+      (rc = check_fptr(acc, "acc")))
+    return rc;
+  if ((rc = check_ws(ws, ws_bytes, ws_accel_f32(n)))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nn = int(n);
+  const float eps2 = float(p->eps * p->eps), G = float(p->G);
+  const Plan pl = plan_f32(n);
+  hipError_t e;
+  if (pl.sj == 1) {
+    e = nbody::launch_accel_f32(pl, nn, pos, mass, eps2, G, acc, 0, st);
+    return e == hipSuccess ? NBODY_OK : hip_fail(e, "accel kernel launch");
+  }
+  float *part = static_cast<float *>(ws);
+  e = nbody::launch_accel_f32(pl, nn, pos, mass, eps2, 1.0f, part,
+                              size_t(3) * n, st);
+  if (e != hipSuccess) return hip_fail(e, "accel kernel launch");
+  e = nbody::launch_reduce_f32(nn, int(pl.sj), part, size_t(3) * n, G, acc, st);
+  return e == hipSuccess ? NBODY_OK : hip_fail(e, "reduce kernel launch");
+}
+
+int nbody_step_f32(int64_t n, int64_t steps, float *pos, float *vel,
+                   float *acc, const float *mass, const nbody_params *p,
+                   unsigned flags, void *ws, size_t ws_bytes, void *stream) {
+  int rc;
+  if ((rc = check_f32(n, p, true))) return rc;
+  if (steps < 0)
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "steps = %lld < 0",
+                (long long)steps);
+  if (flags & ~(NBODY_ACC_VALID | NBODY_HALF_KICK_DRIFT))
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x",
+                flags & ~(NBODY_ACC_VALID | NBODY_HALF_KICK_DRIFT));
+  if ((rc = check_fptr(pos, "pos")) || (rc = check_fptr(vel, "vel")) ||
+      (rc = check_fptr(acc, "acc")) || (rc = check_fptr(mass, "mass")))
+    return rc;
+  if ((rc = check_ws(ws, ws_bytes, ws_step_f32(n)))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nn = int(n);
+  const float eps2 = float(p->eps * p->eps), G = float(p->G);
+  const float dt = float(p->dt), h = 0.5f * dt;
+  const Plan pl = plan_f32(n);
+  float *part = static_cast<float *>(ws);
+  const size_t stride = size_t(3) * n;
+  const bool have_acc = flags & NBODY_ACC_VALID;
+  const unsigned close_flag =
+      (flags & NBODY_HALF_KICK_DRIFT) ? 0u : unsigned(nbody::kClose);
+  hipError_t e;
+  if (!have_acc) {
+    e = nbody::launch_accel_f32(pl, nn, pos, mass, eps2, 1.0f, part, stride, st);
+    if (e != hipSuccess) return hip_fail(e, "accel kernel launch");
+  }
+  if (!have_acc || steps > 0) {
+    e = nbody::launch_update_f32(nn, int(pl.sj), have_acc ? nullptr : part,
+                                 stride, G, acc, have_acc ? nullptr : acc, pos,
+                                 vel, h, dt,
+                                 steps > 0 ? unsigned(nbody::kOpen) : 0u, st);
+    if (e != hipSuccess) return hip_fail(e, "update kernel launch");
+  }
+  for (int64_t t = 0; t < steps; ++t) {
+    e = nbody::launch_accel_f32(pl, nn, pos, mass, eps2, 1.0f, part, stride, st);
+    if (e != hipSuccess) return hip_fail(e, "accel kernel launch");
+    const bool more = t + 1 < steps;
+    e = nbody::launch_update_f32(nn, int(pl.sj), part, stride, G, nullptr, acc,
+                                 pos, vel, h, dt,
+                                 close_flag | (more ? unsigned(nbody::kOpen) : 0u),
+                                 st);
+    if (e != hipSuccess) return hip_fail(e, "update kernel launch");
+  }
+  return NBODY_OK;
 }
 
 }  // extern "C"

@@ -111,4 +111,19 @@ hipError_t launch_diagnostics(int precision, int n, int sj,
                               double eps2, double G, double *blocksum,
                               double *out, hipStream_t st);
 
+// FP32 state (the paper's single-precision variant): plan from
+// make_plan(kAccel, NBODY_MIXED, n).  out + s*stride + c*n + i <- scale *
+// FP32 sum over split s; reduce: out = G * sum_s part (ascending s);
+// update: the KDK / half-kick + drift state update of update_kernel in FP32,
+// in place on x and v (flags kClose / kOpen), no checkpoint record.
+hipError_t launch_accel_f32(const Plan &pl, int n, const float *pos,
+                            const float *mass, float eps2, float scale,
+                            float *out, size_t stride, hipStream_t st);
+hipError_t launch_reduce_f32(int n, int sj, const float *part, size_t stride,
+                             float G, float *out, hipStream_t st);
+hipError_t launch_update_f32(int n, int sj, const float *part, size_t stride,
+                             float G, const float *a_in, float *acc_out,
+                             float *x, float *v, float h, float dt,
+                             unsigned flags, hipStream_t st);
+
 }  // namespace nbody

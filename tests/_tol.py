@@ -179,3 +179,40 @@ def adjoint_bound(oracle, pos, vel, mass, G, eps, dt, steps, gx, gv, ga,
     Bx += bx + 2 * U64 * nrm(gxc + vx)
     Bm += bm + 2 * U64 * np.abs((gmc + vm)[sel])
     return 1.25 * Bx, 1.25 * Bv, 1.25 * Bm
+
+
+def accel_bound_f32(pos, mass, G, eps, rows=None):
+    """Bound on |a_i^gpu - a_i| for the FP32-state path, whose inputs are
+    exactly the FP32 values the oracle gets: each pair term carries 16 u32 of
+    its magnitude, the FP32 sum over sources (each lane's share, the lane
+    butterfly and the splits, depth at most n + 64) gamma_(n+64), and the
+    final scaling by G one more rounding (2 u32 with the reduction's)."""
+    n = mass.size
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    out = np.empty(len(rows))
+    k = 0
+    for blk in _rows_iter(rows, n):
+        d = pos[:, None, :] - pos[:, blk, None]
+        dn = np.sqrt((d * d).sum(axis=0))
+        w = mass[None, :] * (dn * dn + eps * eps) ** -1.5
+        term = w * dn
+        term[np.arange(len(blk)), blk] = 0.0
+        out[k:k + len(blk)] = abs(G) * term.sum(axis=1) * (16 + 2 + n + 64) * U32
+        k += len(blk)
+    return SAFETY * out
+
+
+def lipschitz_accel(pos, mass, G, eps, dx):
+    """max change of each a_i when every x_j moves by at most dx_j (norms):
+    |d(d w)/dd| <= 4 w, so |delta a_i| <= G sum_j m_j 4 w_ij (dx_i + dx_j)."""
+    n = mass.size
+    out = np.empty(n)
+    k = 0
+    for blk in _rows_iter(np.arange(n), n):
+        d = pos[:, None, :] - pos[:, blk, None]
+        dn = np.sqrt((d * d).sum(axis=0))
+        w = mass[None, :] * (dn * dn + eps * eps) ** -1.5
+        w[np.arange(len(blk)), blk] = 0.0
+        out[k:k + len(blk)] = abs(G) * (4.0 * w * (dx[blk, None] + dx[None, :])).sum(axis=1)
+        k += len(blk)
+    return out

@@ -314,3 +314,44 @@ def test_morton_sort_rejects_invalid_arguments(B):
     assert "both NULL" in lib.nbody_last_error().decode()
     assert sort(vel_out=FAKE) == 1
     assert sort(wsb=ws - 8) == 2
+
+
+# ------------------------------------------------------------- FP32 state --
+
+def test_f32_workspace_bytes(B):
+    inv = ctypes.c_size_t(-1).value
+    for n in (1, 255, 1000, 16384, 262144):
+        # the mixed mode's plan with FP32 partials: half its bytes (rounded)
+        step = B.nbody_f32_workspace_bytes(B.NBODY_OP_STEP, n)
+        step64 = B.nbody_workspace_bytes(B.NBODY_OP_STEP, n, 1, 1, B.NBODY_MIXED)
+        assert step % 256 == 0 and step >= 12 * n and abs(2 * step - step64) <= 512
+        acc = B.nbody_f32_workspace_bytes(B.NBODY_OP_ACCEL, n)
+        assert acc == 0 or abs(2 * acc - B.nbody_workspace_bytes(
+            B.NBODY_OP_ACCEL, n, 0, 1, B.NBODY_MIXED)) <= 512
+    assert B.nbody_f32_workspace_bytes(B.NBODY_OP_VJP, 100) == inv
+    assert B.nbody_f32_workspace_bytes(B.NBODY_OP_ACCEL, 0) == inv
+
+
+def test_f32_rejects_invalid_arguments(B):
+    lib = B.load_library()
+    ws = B.nbody_f32_workspace_bytes(B.NBODY_OP_STEP, 1000)
+
+    def acc(n=1000, pos=FAKE, **kw):
+        return lib.nbody_accel_f32(n, _p(pos), _p(FAKE), _p(FAKE), _params(B, **kw),
+                                   _p(FAKE), 1 << 30, None)
+
+    def step(steps=1, flags=0, vel=FAKE, wsb=ws, **kw):
+        return lib.nbody_step_f32(1000, steps, _p(FAKE), _p(vel), _p(FAKE), _p(FAKE),
+                                  _params(B, **kw), flags, _p(FAKE), wsb, None)
+    assert acc(n=0) == 1
+    assert acc(pos=0) == 1
+    assert acc(pos=FAKE + 2) == 1
+    assert acc(eps=0.0) == 1
+    assert acc(eps=1e-30) == 1          # eps^2 underflows FP32
+    assert "FP32" in lib.nbody_last_error().decode()
+    assert acc(G=1e300) == 1
+    assert step(steps=-1) == 1
+    assert step(flags=4) == 1
+    assert step(vel=0) == 1
+    assert step(dt=1e300) == 1
+    assert step(wsb=ws - 4) == 2
