@@ -138,6 +138,20 @@ class Bench:
         B.nbody_step_f32(self.Pf, self.Vf, self.Af, self.Mf, w.G, w.eps, w.dt, w.steps,
                          acc_valid=True, workspace=self.wsf)
 
+    def fwd_adj_every(self, p, K, ck, ws):
+        """Forward with a checkpoint every K steps, then the adjoint."""
+        w, B = self.w, self.B
+        P0, V0, M, GX0 = self.state0(p)
+        self.P.copy_(P0)
+        self.V.copy_(V0)
+        self.A.copy_(self.A0[p])
+        B.nbody_step(self.P, self.V, self.A, M, w.G, w.eps, w.dt, w.steps, p,
+                     acc_valid=True, ckpt=ck, ckpt_every=K, workspace=ws)
+        self.GX.copy_(GX0)
+        self.GV.zero_()
+        B.nbody_step_adjoint(ck, M, self.GX, self.GV, w.G, w.eps, w.dt, w.steps, K,
+                             p, gmass=self.GM, workspace=ws)
+
     def adjoint(self, p):
         w, B = self.w, self.B
         _, _, M, GX0 = self.state0(p)
@@ -487,6 +501,24 @@ def main(argv=None):
                        "fwd_adj_ms": round(sms, 4),
                        "bwd_over_fwd": round((sms - fms) / fms, 3)}
             log("bench: leg %s %s" % (q, legs[q]))
+        # checkpoint interval: K = 1 stores every state (no recomputation),
+        # K = steps keeps one record and recomputes the whole rollout
+        sweep = {}
+        for K in (1, CKPT_EVERY, w.steps):
+            ck = torch.empty(B.nbody_checkpoint_bytes(w.n, w.steps, K) // 8,
+                             dtype=torch.float64, device=bench.dev)
+            wsk = torch.empty(max(B.nbody_workspace_bytes(B.NBODY_OP_STEP, w.n, w.steps, K, p),
+                                  B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, w.n,
+                                                          w.steps, K, p)),
+                              dtype=torch.uint8, device=bench.dev)
+            fn = lambda: bench.fwd_adj_every(p, K, ck, wsk)  # noqa
+            warm(torch, fn)
+            kms, _ = bench.timed(fn, 5, 1)
+            sweep["K%d" % K] = {"fwd_adj_G_int_s": round(n2s / (kms * 1e-3) / 1e9, 1),
+                                "fwd_adj_ms": round(kms, 4),
+                                "checkpoint_MB": round(ck.numel() * 8 / 1e6, 2)}
+        legs["%s_ckpt_every" % p] = sweep
+        log("bench: checkpoint sweep %s" % sweep)
         # FP32 state (forward only: this variant has no adjoint)
         warm(torch, bench.forward_f32)
         fms, _ = bench.timed(bench.forward_f32, 10, 2)

@@ -31,12 +31,15 @@ def B():
     return binding
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_graph_replay_rollout_and_adjoint(B, prec):
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_nf"])
+def test_graph_replay_rollout_and_adjoint(B, oracle, prec):
     say("graph replay", prec)
     dev = torch.device("cuda:0")
     n, S, K = 1024, 20, 5
     pos, vel, mass = inputs.uniform_cube(n, 1001)
+    if prec == "mixed_nf":   # spatial order, so the far form is exercised too
+        o = oracle.morton_order(pos)
+        pos, vel, mass = pos[:, o].copy(), vel[:, o].copy(), mass[o].copy()
     T = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa: E731
     P0, V0, M = T(pos), T(vel), T(mass)
     GX0 = T(inputs.upstream_normal(n, 77))
@@ -91,3 +94,59 @@ def test_graph_replay_rollout_and_adjoint(B, prec):
         junk = B.nbody_accel(P0 * 1.5, M, 1.0, 1e-3, prec)
         torch.cuda.synchronize()
         assert np.isfinite(junk.cpu().numpy()).all()
+
+
+def test_graph_replay_f32_rollout_and_morton_sort(B):
+    say("graph replay f32 + sort")
+    dev = torch.device("cuda:0")
+    n, S = 2000, 15
+    pos, vel, mass = inputs.uniform_cube(n, 1003)
+    T = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa: E731
+    P64, V64, M64 = T(pos), T(vel), T(mass)
+    P0, V0, M = P64.float(), V64.float(), M64.float()
+    P, V, A = torch.empty_like(P0), torch.empty_like(P0), torch.empty_like(P0)
+    WS = torch.empty(B.nbody_f32_workspace_bytes(B.NBODY_OP_STEP, n), dtype=torch.uint8,
+                     device=dev)
+    SW = torch.empty(B.nbody_workspace_bytes(B.NBODY_OP_MORTON_SORT, n, 0, 1, 0),
+                     dtype=torch.uint8, device=dev)
+    perm = torch.empty(n, dtype=torch.int64, device=dev)
+    PS, VS, MS = torch.empty_like(P64), torch.empty_like(P64), torch.empty_like(M64)
+    lib = B.load_library()
+
+    def work():
+        B.nbody_step_f32(P, V, A, M, 1.0, 1e-3, 1e-3, S, workspace=WS)
+        rc = lib.nbody_morton_sort(n, B._ptr(P64), B._ptr(V64), B._ptr(M64),
+                                   B._ptr(perm), B._ptr(PS), B._ptr(VS), B._ptr(MS),
+                                   B._ptr(SW), SW.numel(), B._stream(dev))
+        assert rc == 0
+
+    def reset():
+        P.copy_(P0)
+        V.copy_(V0)
+        for t in (A, PS, VS, MS):
+            t.zero_()
+        perm.zero_()
+
+    reset()
+    work()
+    torch.cuda.synchronize()
+    eager = [t.clone() for t in (P, V, A, perm, PS, VS, MS)]
+    reset()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        work()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        work()
+    torch.cuda.synchronize()
+    for rep in range(4):
+        reset()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip((P, V, A, perm, PS, VS, MS), eager):
+            assert torch.equal(a, b), "replay %d differs" % rep
