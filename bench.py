@@ -54,8 +54,10 @@ MEASURED_TRAFFIC = {("vjp", "mixed"): {"bytes": 24.2e6, "src_sha256": "84cc4c156
 KERNEL_SRC = os.path.join(ROOT, "paper_2203_08263_amd", "csrc", "nbody_kernels.hip")
 DTYPE = {"fp64": "f64", "mixed": "f32-pair/f64-acc",
          "mixed_d64": "f32-pair(f64-diff)/f64-acc",
-         "mixed_nf": "f32-pair(near f64-diff, far recentred)/f64-acc"}
-PRECS = ("fp64", "mixed", "mixed_d64", "mixed_nf")
+         "mixed_nf": "f32-pair(near f64-diff, far recentred)/f64-acc",
+         "mixed_nf64": "near f64-pair, far f32-pair(recentred)/f64-acc"}
+PRECS = ("fp64", "mixed", "mixed_d64", "mixed_nf", "mixed_nf64")
+SORTED = ("mixed_nf", "mixed_nf64")   # run on the bodies in Morton order
 
 
 def log(*a):
@@ -116,7 +118,7 @@ class Bench:
 
     def state0(self, p):
         """(x_0, v_0, m, dL/dx_S) in the body order precision p runs in."""
-        if p == "mixed_nf":
+        if p in SORTED:
             return self.P0s, self.V0s, self.Ms, self.GX0s
         return self.P0, self.V0, self.M, self.GX0
 
@@ -226,10 +228,11 @@ def shape_legs(torch, B, inputs):
     dev = torch.device("cuda:0")
     T = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa
     out = {}
-    for name, precs, kinds in (("plummer65536", ("mixed", "mixed_d64", "fp64", "mixed_nf"),
+    for name, precs, kinds in (("plummer65536", ("mixed", "mixed_d64", "fp64", "mixed_nf",
+                                                 "mixed_nf64"),
                                 ("accel", "diag")),
                                ("plummer262144_vjp", ("mixed", "mixed_d64", "fp64",
-                                                      "mixed_nf"),
+                                                      "mixed_nf", "mixed_nf64"),
                                 ("accel", "vjp", "accel_share8", "vjp_share8"))):
         w = inputs.WORKLOADS[name]
         pos, vel, mass = w.initial_state()
@@ -275,7 +278,7 @@ def shape_legs(torch, B, inputs):
             "TFLOP_s": round(fips * 20 / 1e12, 2),
             "frac_of_vector_peak": round(fips * 20 / 1e12 / PEAK_FP32_TFLOPS, 4)}
         for p in precs:
-            if p == "mixed_nf":
+            if p in SORTED:
                 P, M, Vt, Gt = Ps, Ms, Vs, Gs
             else:
                 P, M, Vt, Gt = P0, M0, V0, G0
@@ -413,7 +416,7 @@ def cpu_baseline(bench, p, gx_gpu, gv_gpu, gm_gpu, x_end, v_end):
     ref = oracle.accel_rows(pos, mass, w.G, w.eps, rows)
     for q in PRECS:
         a = bench.A0[q].cpu().numpy()
-        if q == "mixed_nf":              # back from Morton order
+        if q in SORTED:                  # back from Morton order
             back = np.empty_like(a)
             back[:, bench.perm.cpu().numpy()] = a
             a = back

@@ -80,12 +80,19 @@ typedef struct nbody_params {
  *                   speed when the bodies are in a spatial order
  *                   (nbody_morton_sort); in a random order every run is near
  *                   and results are bitwise those of NBODY_MIXED_D64.
- *                   nbody_diagnostics evaluates W as NBODY_MIXED_D64. */
+ *                   nbody_diagnostics evaluates W as NBODY_MIXED_D64.
+ *  NBODY_MIXED_NF64 as NBODY_MIXED_NF, but near runs use the FP64 pair and add
+ *                   it straight into the FP64 sums, so close pairs -- whose
+ *                   FP32 rounding dominates the mixed modes' error when
+ *                   forces nearly cancel -- carry FP64 error only.  In a
+ *                   random order every run is near and the arithmetic is
+ *                   FP64 throughout.  nbody_diagnostics evaluates W in FP64. */
 enum nbody_precision {
   NBODY_FP64 = 0,
   NBODY_MIXED = 1,
   NBODY_MIXED_D64 = 2,
-  NBODY_MIXED_NF = 3
+  NBODY_MIXED_NF = 3,
+  NBODY_MIXED_NF64 = 4
 };
 
 enum nbody_status {

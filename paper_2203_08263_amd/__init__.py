@@ -12,7 +12,8 @@ input generators) can be imported without torch or the HIP library.
 import importlib
 
 _BINDING = (
-    "NBODY_FP64", "NBODY_MIXED", "NBODY_MIXED_D64", "NBODY_MIXED_NF", "PRECISIONS",
+    "NBODY_FP64", "NBODY_MIXED", "NBODY_MIXED_D64", "NBODY_MIXED_NF",
+    "NBODY_MIXED_NF64", "PRECISIONS",
     "NBodyError", "nbody_morton_sort", "nbody_accel_f32", "nbody_step_f32",
     "nbody_f32_workspace_bytes",
     "nbody_accel", "nbody_accel_vjp", "nbody_step", "nbody_step_adjoint",

@@ -21,8 +21,10 @@ NBODY_FP64 = 0
 NBODY_MIXED = 1
 NBODY_MIXED_D64 = 2
 NBODY_MIXED_NF = 3
+NBODY_MIXED_NF64 = 4
 PRECISIONS = {"fp64": NBODY_FP64, "mixed": NBODY_MIXED,
-              "mixed_d64": NBODY_MIXED_D64, "mixed_nf": NBODY_MIXED_NF}
+              "mixed_d64": NBODY_MIXED_D64, "mixed_nf": NBODY_MIXED_NF,
+              "mixed_nf64": NBODY_MIXED_NF64}
 
 NBODY_OK = 0
 NBODY_ACC_VALID = 1

@@ -39,7 +39,7 @@ size_t dbytes(int64_t count) { return round_up(size_t(count) * sizeof(double)); 
 
 bool valid_precision(int p) {
   return p == NBODY_FP64 || p == NBODY_MIXED || p == NBODY_MIXED_D64 ||
-         p == NBODY_MIXED_NF;
+         p == NBODY_MIXED_NF || p == NBODY_MIXED_NF64;
 }
 
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
@@ -88,7 +88,7 @@ int64_t num_tiles(int64_t n) { return (n + nbody::kThreads - 1) / nbody::kThread
 // it sits at the start of the workspace of every all-pairs operation, the
 // partial sums after it.
 size_t nf_bytes(nbody::KernelKind kind, int prec, int64_t n, int64_t nt) {
-  if (prec != NBODY_MIXED_NF) return 0;
+  if (prec != NBODY_MIXED_NF && prec != NBODY_MIXED_NF64) return 0;
   const Plan pl = nbody::make_plan(kind, prec, nt, n);
   return round_up(nbody::near_far_box_doubles(kind, pl.L, n, nt) * sizeof(double));
 }

@@ -402,7 +402,9 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
 //    (kappa = 1/2: below 6 u32 |d|, the order of one rounding of d itself);
 //  - near runs: the NBODY_MIXED_D64 arithmetic (difference in FP64, rounded
 //    once to FP32), which keeps the close pairs -- whose errors dominate --
-//    as accurate as that mode.
+//    as accurate as that mode; or, for NBODY_MIXED_NF64 (NEAR64), the FP64
+//    pair added straight into the FP64 sums, so the close pairs carry FP64
+//    rounding only.
 // Both forms of every source are staged in LDS; the choice is uniform over
 // each wave (no divergence) and depends only on positions, so results stay
 // deterministic.  All boxes (source runs, the targets of each wave and of
@@ -572,21 +574,21 @@ template <int L>
 __device__ __forceinline__ void target_boxes(const NfBoxes &bx, int nt,
                                              Box &wave, Box &block) {
   constexpr int GW = 64 / L;
-  const int wg = blockIdx.x * (kThreads / 64) + int(threadIdx.x) / 64;
+  // wave index, uniform across the wave (scalar registers and branches)
+  const int wg = __builtin_amdgcn_readfirstlane(
+      int(blockIdx.x) * (kThreads / 64) + int(threadIdx.x) / 64);
+  const bool has = wg * GW < nt;
   block = read_box(bx.block, blockIdx.x);
-  if (wg * GW < nt) {
-    wave = read_box(bx.wave, wg);
-  } else {
-    const double inf = __builtin_huge_val();
+  wave = read_box(bx.wave, has ? wg : 0);  // box 0 always exists
+  const double inf = __builtin_huge_val();
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      wave.lo[c] = inf;
-      wave.hi[c] = -inf;
-    }
+  for (int c = 0; c < 3; ++c) {
+    wave.lo[c] = has ? wave.lo[c] : inf;
+    wave.hi[c] = has ? wave.hi[c] : -inf;
   }
 }
 
-template <int L>
+template <int L, bool NEAR64>
 __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
     int n, int row0, int nt, const double *__restrict__ pos,
     const double *__restrict__ mass, NfBoxes bx, double eps2d, double scale,
@@ -595,7 +597,8 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
   constexpr int PER = kThreads / L;
   constexpr int C = PER < kChunk ? PER : kChunk;
   constexpr int RUN = C * L;  // sources of one chunk run (box granularity)
-  __shared__ Src<NBODY_MIXED_D64> near_tile[kThreads];
+  using NearSrc = Src<NEAR64 ? NBODY_FP64 : NBODY_MIXED_D64>;
+  __shared__ NearSrc near_tile[kThreads];
   __shared__ Src<NBODY_MIXED> far_tile[kThreads];
 
   const int tid = threadIdx.x;
@@ -624,12 +627,13 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
     const double xj = valid ? pos[j] : 0.0;
     const double yj = valid ? pos[n + j] : 0.0;
     const double zj = valid ? pos[2 * n + j] : 0.0;
-    const float mj = valid ? float(mass[j]) : 0.0f;
-    Src<NBODY_MIXED_D64> bn{};
+    const double mj64 = valid ? mass[j] : 0.0;
+    const float mj = float(mj64);
+    NearSrc bn{};
     bn.x = xj;
     bn.y = yj;
     bn.z = zj;
-    bn.m = mj;
+    if constexpr (NEAR64) bn.m = mj64; else bn.m = mj;
     Src<NBODY_MIXED> bf{};
     if (valid) {
       bf.x = float(xj - c[0]);
@@ -645,6 +649,14 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
 
     for (int u0 = 0; u0 < PER; u0 += C) {
       const bool far = (far_mask >> (u0 / C)) & 1u;  // run u0 / C of the tile
+      if (NEAR64 && !far) {
+#pragma unroll 4
+        for (int u = 0; u < C; ++u) {
+          const NearSrc s = near_tile[(u0 + u) * L + q];
+          pair_f64(s.x - xi, s.y - yi, s.z - zi, double(s.m), eps2d, ax, ay, az);
+        }
+        continue;
+      }
       float fx = 0.0f, fy = 0.0f, fz = 0.0f;
       if (far) {
 #pragma unroll
@@ -652,12 +664,12 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
           const Src<NBODY_MIXED> s = far_tile[(u0 + u) * L + q];
           pair_f32(s.x - xr, s.y - yr, s.z - zr, s.m, eps2, fx, fy, fz);
         }
-      } else {
+      } else if constexpr (!NEAR64) {
 #pragma unroll
         for (int u = 0; u < C; ++u) {
-          const Src<NBODY_MIXED_D64> s = near_tile[(u0 + u) * L + q];
-          pair_f32(float(s.x - xi), float(s.y - yi), float(s.z - zi), s.m, eps2,
-                   fx, fy, fz);
+          const NearSrc s = near_tile[(u0 + u) * L + q];
+          pair_f32(float(s.x - xi), float(s.y - yi), float(s.z - zi), float(s.m),
+                   eps2, fx, fy, fz);
         }
       }
       ax += double(fx);
@@ -677,7 +689,7 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
   }
 }
 
-template <int L>
+template <int L, bool NEAR64>
 __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
     int n, int row0, int nt, const double *__restrict__ pos,
     const double *__restrict__ mass, const double *__restrict__ gacc,
@@ -688,7 +700,8 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
   constexpr int PER = kThreads / L;
   constexpr int C = PER < kVjpChunk ? PER : kVjpChunk;
   constexpr int RUN = C * L;
-  __shared__ VSrc<NBODY_MIXED_D64> near_tile[kThreads];
+  using NearSrc = VSrc<NEAR64 ? NBODY_FP64 : NBODY_MIXED_D64>;
+  __shared__ NearSrc near_tile[kThreads];
   __shared__ VSrc<NBODY_MIXED> far_tile[kThreads];
 
   const int tid = threadIdx.x;
@@ -701,10 +714,14 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
   const double xk = ok ? pos[gk] : 0.0;
   const double yk = ok ? pos[n + gk] : 0.0;
   const double zk = ok ? pos[2 * n + gk] : 0.0;
-  const float mk = ok ? float(mass[gk]) : 0.0f;
-  const float gkx = ok ? float(gacc[gk]) : 0.0f;
-  const float gky = ok ? float(gacc[n + gk]) : 0.0f;
-  const float gkz = ok ? float(gacc[2 * n + gk]) : 0.0f;
+  const double mk64 = ok ? mass[gk] : 0.0;
+  const double gkx64 = ok ? gacc[gk] : 0.0;
+  const double gky64 = ok ? gacc[n + gk] : 0.0;
+  const double gkz64 = ok ? gacc[2 * n + gk] : 0.0;
+  const float mk = float(mk64);
+  const float gkx = float(gkx64);
+  const float gky = float(gky64);
+  const float gkz = float(gkz64);
   Box wave, block;
   target_boxes<L>(bx, nt, wave, block);
   double c[3];
@@ -721,18 +738,29 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
     const double xj = valid ? pos[j] : 0.0;
     const double yj = valid ? pos[n + j] : 0.0;
     const double zj = valid ? pos[2 * n + j] : 0.0;
-    const float mj = valid ? float(mass[j]) : 0.0f;
-    const float gjx = valid ? float(gacc[j]) : 0.0f;
-    const float gjy = valid ? float(gacc[n + j]) : 0.0f;
-    const float gjz = valid ? float(gacc[2 * n + j]) : 0.0f;
-    VSrc<NBODY_MIXED_D64> bn{};
+    const double mj64 = valid ? mass[j] : 0.0;
+    const double gjx64 = valid ? gacc[j] : 0.0;
+    const double gjy64 = valid ? gacc[n + j] : 0.0;
+    const double gjz64 = valid ? gacc[2 * n + j] : 0.0;
+    const float mj = float(mj64);
+    const float gjx = float(gjx64);
+    const float gjy = float(gjy64);
+    const float gjz = float(gjz64);
+    NearSrc bn{};
     bn.x = xj;
     bn.y = yj;
     bn.z = zj;
-    bn.m = mj;
-    bn.gx = gjx;
-    bn.gy = gjy;
-    bn.gz = gjz;
+    if constexpr (NEAR64) {
+      bn.m = mj64;
+      bn.gx = gjx64;
+      bn.gy = gjy64;
+      bn.gz = gjz64;
+    } else {
+      bn.m = mj;
+      bn.gx = gjx;
+      bn.gy = gjy;
+      bn.gz = gjz;
+    }
     VSrc<NBODY_MIXED> bf{};
     if (valid) {
       bf.x = float(xj - c[0]);
@@ -751,6 +779,16 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
 
     for (int u0 = 0; u0 < PER; u0 += C) {
       const bool far = (far_mask >> (u0 / C)) & 1u;
+      if (NEAR64 && !far) {
+#pragma unroll 2
+        for (int u = 0; u < C; ++u) {
+          const NearSrc s = near_tile[(u0 + u) * L + q];
+          vjp_pair<double>(s.x - xk, s.y - yk, s.z - zk, double(s.m),
+                           double(s.gx), double(s.gy), double(s.gz), mk64, gkx64,
+                           gky64, gkz64, eps2d, sx, sy, sz, sm);
+        }
+        continue;
+      }
       float fx = 0.0f, fy = 0.0f, fz = 0.0f, fm = 0.0f;
       if (far) {
 #pragma unroll
@@ -759,13 +797,13 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
           vjp_pair<float>(s.x - xr, s.y - yr, s.z - zr, s.m, s.gx, s.gy, s.gz,
                           mk, gkx, gky, gkz, eps2, fx, fy, fz, fm);
         }
-      } else {
+      } else if constexpr (!NEAR64) {
 #pragma unroll
         for (int u = 0; u < C; ++u) {
-          const VSrc<NBODY_MIXED_D64> s = near_tile[(u0 + u) * L + q];
+          const NearSrc s = near_tile[(u0 + u) * L + q];
           vjp_pair<float>(float(s.x - xk), float(s.y - yk), float(s.z - zk),
-                          s.m, s.gx, s.gy, s.gz, mk, gkx, gky, gkz, eps2, fx, fy,
-                          fz, fm);
+                          float(s.m), float(s.gx), float(s.gy), float(s.gz), mk,
+                          gkx, gky, gkz, eps2, fx, fy, fz, fm);
         }
       }
       sx += double(fx);
@@ -782,10 +820,17 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
   double tz = group_sum<L>(sz);
   const double tm = group_sum<L>(sm);
   if (q == 0 && ok) {
-    if (gk >= jbeg && gk < jend) {  // this split holds the self pair (e = 0)
-      tx -= self_pair_term<float>(mk, gkx, eps2);
-      ty -= self_pair_term<float>(mk, gky, eps2);
-      tz -= self_pair_term<float>(mk, gkz, eps2);
+    if (gk >= jbeg && gk < jend) {  // this split holds the self pair (e = 0),
+      // always in a near run (its run box contains x_k, gap 0)
+      if constexpr (NEAR64) {
+        tx -= self_pair_term<double>(mk64, gkx64, eps2d);
+        ty -= self_pair_term<double>(mk64, gky64, eps2d);
+        tz -= self_pair_term<double>(mk64, gkz64, eps2d);
+      } else {
+        tx -= self_pair_term<float>(mk, gkx, eps2);
+        ty -= self_pair_term<float>(mk, gky, eps2);
+        tz -= self_pair_term<float>(mk, gkz, eps2);
+      }
     }
     ox[k] = scale * tx;
     ox[nt + k] = scale * ty;
@@ -1403,24 +1448,24 @@ hipError_t launch_accel(const Plan &pl, int precision, int n, int row0, int nt,
                         double eps2, double scale, double *out, size_t stride,
                         hipStream_t st) {
   switch (precision) {
-    case NBODY_MIXED_NF: {
+    case NBODY_MIXED_NF:
+    case NBODY_MIXED_NF64: {
       if (pl.R != 1) return hipErrorInvalidValue;
       NfBoxes bx;
       const hipError_t e = launch_nf_boxes(kAccel, pl.L, n, row0, nt, pos, boxes, bx, st);
       if (e != hipSuccess) return e;
       const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
       const int jc = int(pl.jchunk);
-      if (pl.L == 1)
-        accel_nf_kernel<1><<<grid, kThreads, 0, st>>>(n, row0, nt, pos, mass, bx,
-                                                      eps2, scale, jc, out, stride);
-      else if (pl.L == 4)
-        accel_nf_kernel<4><<<grid, kThreads, 0, st>>>(n, row0, nt, pos, mass, bx,
-                                                      eps2, scale, jc, out, stride);
-      else if (pl.L == 16)
-        accel_nf_kernel<16><<<grid, kThreads, 0, st>>>(n, row0, nt, pos, mass, bx,
-                                                       eps2, scale, jc, out, stride);
-      else
-        return hipErrorInvalidValue;
+#define NBODY_ACCEL_NF(L_, N64_)                                                 \
+  accel_nf_kernel<L_, N64_><<<grid, kThreads, 0, st>>>(n, row0, nt, pos, mass,   \
+                                                       bx, eps2, scale, jc, out, \
+                                                       stride)
+      const bool n64 = precision == NBODY_MIXED_NF64;
+      if (pl.L == 1) { if (n64) NBODY_ACCEL_NF(1, true); else NBODY_ACCEL_NF(1, false); }
+      else if (pl.L == 4) { if (n64) NBODY_ACCEL_NF(4, true); else NBODY_ACCEL_NF(4, false); }
+      else if (pl.L == 16) { if (n64) NBODY_ACCEL_NF(16, true); else NBODY_ACCEL_NF(16, false); }
+      else return hipErrorInvalidValue;
+#undef NBODY_ACCEL_NF
       return hipGetLastError();
     }
     case NBODY_FP64:
@@ -1441,27 +1486,24 @@ hipError_t launch_vjp(const Plan &pl, int precision, int n, int row0, int nt,
                       double *boxes, double eps2, double scale, double *ox,
                       double *om, size_t stride, hipStream_t st) {
   switch (precision) {
-    case NBODY_MIXED_NF: {
+    case NBODY_MIXED_NF:
+    case NBODY_MIXED_NF64: {
       if (pl.R != 1) return hipErrorInvalidValue;
       NfBoxes bx;
       const hipError_t e = launch_nf_boxes(kVjp, pl.L, n, row0, nt, pos, boxes, bx, st);
       if (e != hipSuccess) return e;
       const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
       const int jc = int(pl.jchunk);
-      if (pl.L == 1)
-        vjp_nf_kernel<1><<<grid, kThreads, 0, st>>>(n, row0, nt, pos, mass, gacc,
-                                                    bx, eps2, scale, jc, ox, om,
-                                                    stride);
-      else if (pl.L == 4)
-        vjp_nf_kernel<4><<<grid, kThreads, 0, st>>>(n, row0, nt, pos, mass, gacc,
-                                                    bx, eps2, scale, jc, ox, om,
-                                                    stride);
-      else if (pl.L == 16)
-        vjp_nf_kernel<16><<<grid, kThreads, 0, st>>>(n, row0, nt, pos, mass, gacc,
-                                                     bx, eps2, scale, jc, ox, om,
-                                                     stride);
-      else
-        return hipErrorInvalidValue;
+#define NBODY_VJP_NF(L_, N64_)                                                   \
+  vjp_nf_kernel<L_, N64_><<<grid, kThreads, 0, st>>>(n, row0, nt, pos, mass,     \
+                                                     gacc, bx, eps2, scale, jc,  \
+                                                     ox, om, stride)
+      const bool n64 = precision == NBODY_MIXED_NF64;
+      if (pl.L == 1) { if (n64) NBODY_VJP_NF(1, true); else NBODY_VJP_NF(1, false); }
+      else if (pl.L == 4) { if (n64) NBODY_VJP_NF(4, true); else NBODY_VJP_NF(4, false); }
+      else if (pl.L == 16) { if (n64) NBODY_VJP_NF(16, true); else NBODY_VJP_NF(16, false); }
+      else return hipErrorInvalidValue;
+#undef NBODY_VJP_NF
       return hipGetLastError();
     }
     case NBODY_FP64:
@@ -1497,7 +1539,8 @@ hipError_t launch_potential(const Plan &pl, int precision, int n,
       return hipErrorInvalidValue;                                            \
   } while (0)
   switch (precision) {
-    case NBODY_FP64: NBODY_POT(NBODY_FP64); break;
+    case NBODY_FP64:
+    case NBODY_MIXED_NF64: NBODY_POT(NBODY_FP64); break;
     case NBODY_MIXED: NBODY_POT(NBODY_MIXED); break;
     case NBODY_MIXED_D64:
     case NBODY_MIXED_NF: NBODY_POT(NBODY_MIXED_D64); break;
@@ -1515,6 +1558,7 @@ hipError_t launch_diagnostics(int precision, int n, int sj,
   const int nblocks = (n + kThreads - 1) / kThreads;
   switch (precision) {
     case NBODY_FP64:
+    case NBODY_MIXED_NF64:
       diag_block_kernel<NBODY_FP64><<<nblocks, kThreads, 0, st>>>(
           n, sj, phi_part, pos, vel, mass, eps2, blocksum);
       break;

@@ -47,7 +47,7 @@ def _delta(precision, xn, blk, dn):
         return U32 * (xn[blk, None] + xn[None, :] + dn)
     if precision == "mixed_d64":
         return U32 * dn
-    if precision == "mixed_nf":
+    if precision in ("mixed_nf", "mixed_nf64"):   # nf64: FP64 near runs, within it
         return NF_DELTA * U32 * dn
     if precision == "fp64":
         return 0.0

@@ -54,6 +54,7 @@ def test_header_enums_match_binding(B):
     for name, val in [("NBODY_FP64", B.NBODY_FP64), ("NBODY_MIXED", B.NBODY_MIXED),
                       ("NBODY_MIXED_D64", B.NBODY_MIXED_D64),
                       ("NBODY_MIXED_NF", B.NBODY_MIXED_NF),
+                      ("NBODY_MIXED_NF64", B.NBODY_MIXED_NF64),
                       ("NBODY_OP_MORTON_SORT", B.NBODY_OP_MORTON_SORT),
                       ("NBODY_OP_STEP_ADJOINT", B.NBODY_OP_STEP_ADJOINT)]:
         m = re.search(r"\b%s\s*=\s*(\d+)" % name, txt)
@@ -99,7 +100,7 @@ def test_workspace_bytes(B):
         assert B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, 100, 50, 0, prec) == inv
     assert B.nbody_workspace_bytes(7, 100, 0, 1, 0) == inv
     assert B.nbody_workspace_bytes(0, 0, 0, 1, 0) == inv
-    assert B.nbody_workspace_bytes(0, 100, 0, 1, 4) == inv
+    assert B.nbody_workspace_bytes(0, 100, 0, 1, 5) == inv
     assert B.nbody_workspace_bytes(0, B.NBODY_MAX_N + 1, 0, 1, 0) == inv
     # fewer segment positions are needed when steps < ckpt_every
     a = B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, 1000, 3, 10, 0)
@@ -133,7 +134,7 @@ def _accel(B, n=64, pos=FAKE, mass=FAKE, acc=FAKE, prec=0, ws=None, wsb=0, **kw)
     (dict(acc=0), "acc is NULL"), (dict(pos=FAKE + 4), "aligned"),
     (dict(eps=0.0), "eps"), (dict(eps=-1.0), "eps"), (dict(eps=math.nan), "eps"),
     (dict(eps=1e-200), "eps^2"), (dict(G=math.inf), "G is not finite"),
-    (dict(prec=4), "precision"), (dict(prec=-1), "precision"),
+    (dict(prec=5), "precision"), (dict(prec=-1), "precision"),
 ])
 def test_accel_rejects_invalid_arguments(B, kw, msg):
     rc = _accel(B, **kw)
@@ -203,7 +204,7 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
 def test_rows_workspace_matches_full_call(B):
     # the plan for all n rows is the whole-system plan (same split count, so
     # the same workspace and, on the GPU, bitwise the same result)
-    for prec in (0, 1, 2, 3):
+    for prec in (0, 1, 2, 3, 4):
         for n in (1, 255, 256, 1000, 3001, 16384, 65536, 262144, 1 << 20):
             for op in (B.NBODY_OP_ACCEL, B.NBODY_OP_VJP):
                 assert (B.nbody_rows_workspace_bytes(op, n, n, prec)
@@ -212,7 +213,7 @@ def test_rows_workspace_matches_full_call(B):
 
 def test_rows_workspace_bytes(B):
     inv = ctypes.c_size_t(-1).value
-    for prec in (0, 1, 2, 3):
+    for prec in (0, 1, 2, 3, 4):
         assert B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 1000, 0, prec) == 0
         for n, rows in ((262144, 32768), (262144, 1), (1 << 28, 1), (5000, 77)):
             a = B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, n, rows, prec)
@@ -220,13 +221,13 @@ def test_rows_workspace_bytes(B):
             # at most 64 source splits of FP64 partials (plus the bounding
             # boxes of the near / far mode)
             boxes = ((-(-n // 16) + 2 * -(-rows // 4)) * 48 + 255) // 256 * 256 \
-                if prec == 3 else 0
+                if prec in (3, 4) else 0
             assert a % 256 == 0 and a <= 64 * 3 * rows * 8 + 256 + boxes
             assert v % 256 == 0 and v <= 64 * 4 * rows * 8 + 256 + boxes
         assert B.nbody_rows_workspace_bytes(B.NBODY_OP_STEP, 1000, 10, prec) == inv
         assert B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 1000, 1001, prec) == inv
         assert B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 1000, -1, prec) == inv
-    assert B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 1000, 10, 4) == inv
+    assert B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 1000, 10, 5) == inv
 
 
 def test_rows_reject_invalid_ranges(B):
@@ -284,6 +285,10 @@ def test_near_far_workspace_adds_box_scratch(B):
         # rows: boxes over all n sources plus the target rows' own
         r = B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, n, max(1, n // 8), 3)
         assert r > B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, n, max(1, n // 8), 1)
+        # the FP64-near variant needs exactly the same scratch
+        for op in (B.NBODY_OP_ACCEL, B.NBODY_OP_VJP, B.NBODY_OP_STEP):
+            assert (B.nbody_workspace_bytes(op, n, 10, 1, B.NBODY_MIXED_NF64)
+                    == B.nbody_workspace_bytes(op, n, 10, 1, B.NBODY_MIXED_NF))
         # the potential of the diagnostics uses the D64 arithmetic, no boxes
         assert (B.nbody_workspace_bytes(B.NBODY_OP_DIAGNOSTICS, n, 0, 1, 3)
                 == B.nbody_workspace_bytes(B.NBODY_OP_DIAGNOSTICS, n, 0, 1, 2))
@@ -293,7 +298,7 @@ def test_morton_workspace_bytes(B):
     for n, npad in ((1, 1), (2, 2), (1000, 1024), (1024, 1024), (1025, 2048),
                     (262144, 262144)):
         want = _tile_boxes(n) + 256 + (npad * 8 + 255) // 256 * 256
-        for prec in (0, 1, 2, 3):
+        for prec in (0, 1, 2, 3, 4):
             assert B.nbody_workspace_bytes(B.NBODY_OP_MORTON_SORT, n, 0, 1, prec) == want
 
 

@@ -19,7 +19,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 U32, U64 = 2.0 ** -24, 2.0 ** -53
-PRECS = ["fp64", "mixed", "mixed_d64", "mixed_nf"]
+PRECS = ["fp64", "mixed", "mixed_d64", "mixed_nf", "mixed_nf64"]
 
 
 def say(*a):

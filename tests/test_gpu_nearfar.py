@@ -9,6 +9,9 @@ Morton sort it relies on for speed.
   path) far tiles appear: NF differs from D64 and stays within its own
   bound (coordinate error < 6 u32 |d| per pair) against the oracle, for the
   acceleration, the VJP, row ranges, a rollout and its adjoint.
+* NBODY_MIXED_NF64 (near runs in FP64): in a random order every run is near
+  and the whole sum meets the FP64 bounds; in Morton order it meets the NF
+  bounds, with the close pairs in FP64.
 """
 import sys
 
@@ -107,25 +110,44 @@ def test_random_order_is_all_near_equals_d64(B, dev, n):
     assert np.array_equal(N(gm_nf), N(gm_d))
 
 
+@pytest.mark.parametrize("n", [300, 3001])
+def test_nf64_random_order_is_fp64(B, dev, oracle, n):
+    say("nf64 random order", n)
+    pos, _, mass = inputs.uniform_cube(n, 1420 + n)
+    g = inputs.upstream_normal(n, 1470 + n)
+    P, M, Gt = T(pos, dev), T(mass, dev), T(g, dev)
+    a = N(B.nbody_accel(P, M, 1.0, 1e-3, "mixed_nf64"))
+    _check_bound(a, oracle.accel(pos, mass, 1.0, 1e-3),
+                 _tol.accel_bound(pos, mass, 1.0, 1e-3, "fp64"), "accel")
+    gx, gm = B.nbody_accel_vjp(P, M, Gt, 1.0, 1e-3, "mixed_nf64")
+    rx, rm = oracle.accel_vjp(pos, mass, g, 1.0, 1e-3)
+    bx, bm = _tol.vjp_bound(pos, mass, g, 1.0, 1e-3, "fp64")
+    _check_bound(N(gx), rx, bx, "dL/dx")
+    assert np.all(np.abs(N(gm) - rm) <= bm), "dL/dm"
+
+
+@pytest.mark.parametrize("prec", ["mixed_nf", "mixed_nf64"])
 @pytest.mark.parametrize("n", [2000, 16384])
-def test_sorted_accel_and_vjp_vs_oracle(B, dev, oracle, n):
-    say("nf sorted", n)
+def test_sorted_accel_and_vjp_vs_oracle(B, dev, oracle, n, prec):
+    say(prec, "sorted", n)
     pos, _, mass = _sorted_cube(oracle, n, 1500 + n)
     g = inputs.upstream_normal(n, 1550 + n)
     P, M, Gt = T(pos, dev), T(mass, dev), T(g, dev)
-    a_nf = N(B.nbody_accel(P, M, 1.0, 1e-3, "mixed_nf"))
+    a_nf = N(B.nbody_accel(P, M, 1.0, 1e-3, prec))
     a_d = N(B.nbody_accel(P, M, 1.0, 1e-3, "mixed_d64"))
-    assert not np.array_equal(a_nf, a_d)        # far tiles were taken
+    a_64 = N(B.nbody_accel(P, M, 1.0, 1e-3, "fp64"))
+    assert not np.array_equal(a_nf, a_d)        # far runs were taken
+    assert not np.array_equal(a_nf, a_64)
     rows = np.arange(n) if n <= 4096 else inputs.subset_rows(n, 1024, 1600)
     ra = oracle.accel_rows(pos, mass, 1.0, 1e-3, rows)
     err = _check_bound(a_nf[:, rows], ra,
-                       _tol.accel_bound(pos, mass, 1.0, 1e-3, "mixed_nf", rows), "accel")
+                       _tol.accel_bound(pos, mass, 1.0, 1e-3, prec, rows), "accel")
     rel = err / np.linalg.norm(ra, axis=0)
     say("  accel E_max %.2e E_med %.2e" % (rel.max(), np.median(rel)))
-    gx, gm = B.nbody_accel_vjp(P, M, Gt, 1.0, 1e-3, "mixed_nf")
+    gx, gm = B.nbody_accel_vjp(P, M, Gt, 1.0, 1e-3, prec)
     gx, gm = N(gx)[:, rows], N(gm)[rows]
     rx, rm = oracle.accel_vjp_rows(pos, mass, g, 1.0, 1e-3, rows)
-    bx, bm = _tol.vjp_bound(pos, mass, g, 1.0, 1e-3, "mixed_nf", rows)
+    bx, bm = _tol.vjp_bound(pos, mass, g, 1.0, 1e-3, prec, rows)
     _check_bound(gx, rx, bx, "dL/dx")
     assert np.all(np.abs(gm - rm) <= bm), "dL/dm"
 
@@ -145,9 +167,10 @@ def test_sorted_rows_and_determinism(B, dev, oracle):
                  _tol.accel_bound(pos, mass, 1.0, 1e-3, "mixed_nf", rows), "rows")
 
 
-def test_sorted_rollout_and_adjoint_vs_oracle(B, dev, oracle):
+@pytest.mark.parametrize("prec", ["mixed_nf", "mixed_nf64"])
+def test_sorted_rollout_and_adjoint_vs_oracle(B, dev, oracle, prec):
     n, S, K = 2048, 6, 4
-    say("nf rollout + adjoint", n)
+    say(prec, "rollout + adjoint", n)
     pos, vel, mass = _sorted_cube(oracle, n, 1800)
     gxT = inputs.upstream_normal(n, 1801)
     gvT = inputs.upstream_normal(n, 1802)
@@ -155,39 +178,40 @@ def test_sorted_rollout_and_adjoint_vs_oracle(B, dev, oracle):
     A = torch.empty_like(P)
     ck = torch.empty(B.nbody_checkpoint_bytes(n, S, K) // 8, dtype=torch.float64,
                      device=dev)
-    B.nbody_step(P, V, A, M, 1.0, 1e-3, 1e-3, S, "mixed_nf", ckpt=ck, ckpt_every=K)
+    B.nbody_step(P, V, A, M, 1.0, 1e-3, 1e-3, S, prec, ckpt=ck, ckpt_every=K)
     x_ref, v_ref, _ = oracle.step(pos, vel, mass, 1.0, 1e-3, 1e-3, S)
     dx = np.linalg.norm(N(P) - x_ref) / np.linalg.norm(x_ref)
     dv = np.linalg.norm(N(V) - v_ref) / np.linalg.norm(v_ref)
     say("  state rel err x %.2e v %.2e" % (dx, dv))
     assert dx < 1e-9 and dv < 1e-5
     gx, gv = T(gxT, dev), T(gvT, dev)
-    gx, gv, gm = B.nbody_step_adjoint(ck, M, gx, gv, 1.0, 1e-3, 1e-3, S, K, "mixed_nf")
+    gx, gv, gm = B.nbody_step_adjoint(ck, M, gx, gv, 1.0, 1e-3, 1e-3, S, K, prec)
     ox, ov, om = oracle.step_adjoint(pos, vel, mass, 1.0, 1e-3, 1e-3, S, gxT, gvT)
     bx, bv, bm = _tol.adjoint_bound(oracle, pos, vel, mass, 1.0, 1e-3, 1e-3, S,
-                                    gxT, gvT, None, "mixed_nf")
+                                    gxT, gvT, None, prec)
     _check_bound(N(gx), ox, bx, "dL/dx0")
     _check_bound(N(gv), ov, bv, "dL/dv0")
     assert np.all(np.abs(N(gm) - om) <= bm), "dL/dm"
 
 
-def test_plummer262144_sorted_share(B, dev, oracle):
+@pytest.mark.parametrize("prec", ["mixed_nf", "mixed_nf64"])
+def test_plummer262144_sorted_share(B, dev, oracle, prec):
     # the clustered Plummer system in Morton order: accel and VJP on sampled
     # rows of the whole system against the oracle
     w = inputs.WORKLOADS["plummer262144_vjp"]
-    say("nf", w.name)
+    say(prec, w.name)
     pos, _, mass = w.initial_state()
     o = oracle.morton_order(pos)
     pos, mass = pos[:, o].copy(), mass[o].copy()
     g = inputs.upstream_normal(w.n, w.seed + 400)
     P, M, Gt = T(pos, dev), T(mass, dev), T(g, dev)
     rows = w.rows(256)
-    a = N(B.nbody_accel(P, M, w.G, w.eps, "mixed_nf"))[:, rows]
+    a = N(B.nbody_accel(P, M, w.G, w.eps, prec))[:, rows]
     _check_bound(a, oracle.accel_rows(pos, mass, w.G, w.eps, rows),
-                 _tol.accel_bound(pos, mass, w.G, w.eps, "mixed_nf", rows), "accel")
-    gx, gm = B.nbody_accel_vjp(P, M, Gt, w.G, w.eps, "mixed_nf")
+                 _tol.accel_bound(pos, mass, w.G, w.eps, prec, rows), "accel")
+    gx, gm = B.nbody_accel_vjp(P, M, Gt, w.G, w.eps, prec)
     gx, gm = N(gx)[:, rows], N(gm)[rows]
     rx, rm = oracle.accel_vjp_rows(pos, mass, g, w.G, w.eps, rows)
-    bx, bm = _tol.vjp_bound(pos, mass, g, w.G, w.eps, "mixed_nf", rows)
+    bx, bm = _tol.vjp_bound(pos, mass, g, w.G, w.eps, prec, rows)
     _check_bound(gx, rx, bx, "dL/dx")
     assert np.all(np.abs(gm - rm) <= bm), "dL/dm"

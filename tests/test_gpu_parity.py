@@ -17,7 +17,7 @@ from paper_2203_08263_amd import inputs
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp64", "mixed", "mixed_d64", "mixed_nf"]
+PRECS = ["fp64", "mixed", "mixed_d64", "mixed_nf", "mixed_nf64"]
 SIZES = [1, 2, 3, 64, 255, 256, 257, 1000, 2049, 5003]
 
 
