@@ -50,8 +50,10 @@ FLOPS_PER_PAIR = {"accel": 20, "vjp": 48, "diag": 13}
 # 64 MiB device copy; profiles/vjp_kernel_cube16384_mixed_traffic.md).  They
 # describe the kernel source they were taken on (first 16 hex digits of its
 # SHA-256) and are reported as null for any other source.
-MEASURED_TRAFFIC = {("vjp", "mixed"): {"bytes": 24.2e6, "src_sha256": "84cc4c1565e625bd"}}
-KERNEL_SRC = os.path.join(ROOT, "paper_2203_08263_amd", "csrc", "nbody_kernels.hip")
+MEASURED_TRAFFIC = {("vjp", "mixed"): {"bytes": 24.2e6, "src_sha256": "e997b302a82f2f7d"}}
+# the sources that define the all-pairs VJP / forward kernels of the roofline
+KERNEL_SRC = [os.path.join(ROOT, "paper_2203_08263_amd", "csrc", f)
+              for f in ("nbody_kernels.hip", "nbody_device.h")]
 DTYPE = {"fp64": "f64", "mixed": "f32-pair/f64-acc",
          "mixed_d64": "f32-pair(f64-diff)/f64-acc",
          "mixed_nf": "f32-pair(near f64-diff, far recentred)/f64-acc",
@@ -184,6 +186,16 @@ class Bench:
         return e0.elapsed_time(e1) / reps, 1e3 * wall / reps
 
 
+def kernel_src_hash():
+    """sha256 prefix of the kernel sources (concatenated in KERNEL_SRC order)."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def roofline(bench, p, kind):
     """Average launch duration (HIP events on the launch stream) of the
     all-pairs kernel of `kind` at the workload's size, and its position
@@ -202,10 +214,8 @@ def roofline(bench, p, kind):
     traffic = None
     rec = MEASURED_TRAFFIC.get((kind, p))
     if rec is not None:
-        import hashlib
-        with open(KERNEL_SRC, "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest()[:16] == rec["src_sha256"]:
-                traffic = rec["bytes"]
+        if kernel_src_hash() == rec["src_sha256"]:
+            traffic = rec["bytes"]
     achieved = flops / (ms * 1e-3) / 1e12
     peak = PEAK_FP64_TFLOPS if p == "fp64" else PEAK_FP32_TFLOPS
     return {"kernel": "%s (%s), N=%d" % ({"accel": "accel_kernel", "vjp": "vjp_kernel"}[kind],

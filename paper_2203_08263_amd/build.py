@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnbody_hip.so")
-SOURCES = ["nbody_kernels.hip", "nbody_api.hip"]
+SOURCES = ["nbody_kernels.hip", "nbody_nearfar.hip", "nbody_f32.hip", "nbody_api.hip"]
 MICROBENCH = os.path.join(HERE, "valu_microbench")
 ARCH = "gfx950"
 

@@ -1,0 +1,161 @@
+// Device-side building blocks shared by the gfx950 kernel sources of the
+// all-pairs N-body library: the pair arithmetic of the force and its VJP,
+// the LDS source-tile layouts, the lane butterfly sum and launch helpers.
+// Everything lives in an unnamed namespace, so each kernel source gets its
+// own inlined copy.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nbody_internal.h"
+#include "../../include/nbody.h"
+
+namespace nbody {
+namespace {
+
+constexpr int kChunk = 32;        // FP32 sources per FP64 flush (forward)
+constexpr int kVjpChunk = 16;     // FP32 sources per FP64 flush (VJP)
+constexpr int kBodyThreads = 64;  // threads per workgroup, per-body kernels
+
+// -------------------------------------------------------------- arithmetic --
+
+// 1/sqrt(s) in FP64: hardware estimate (about 23 correct bits) refined by two
+// Newton steps y <- y (3 - s y^2) / 2, written as y + y (1/2 - (s/2) y y).
+__device__ __forceinline__ double rsqrt_f64(double s) {
+  double y = __builtin_amdgcn_rsq(s);
+  const double hs = 0.5 * s;
+  double e = fma(-(hs * y), y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-(hs * y), y, 0.5);
+  y = fma(y, e, y);
+  return y;
+}
+
+__device__ __forceinline__ float rsqrt_f32(float s) {
+  return __builtin_amdgcn_rsqf(s);
+}
+
+// One source j acting on one target: a += m_j d (|d|^2 + eps^2)^-3/2.
+__device__ __forceinline__ void pair_f64(double dx, double dy, double dz,
+                                         double m, double eps2, double &ax,
+                                         double &ay, double &az) {
+  double s = fma(dx, dx, eps2);
+  s = fma(dy, dy, s);
+  s = fma(dz, dz, s);
+  const double y = rsqrt_f64(s);
+  const double w = (m * y) * (y * y);
+  ax = fma(w, dx, ax);
+  ay = fma(w, dy, ay);
+  az = fma(w, dz, az);
+}
+
+__device__ __forceinline__ void pair_f32(float dx, float dy, float dz, float m,
+                                         float eps2, float &ax, float &ay,
+                                         float &az) {
+  float s = fmaf(dx, dx, eps2);
+  s = fmaf(dy, dy, s);
+  s = fmaf(dz, dz, s);
+  const float y = rsqrt_f32(s);
+  const float w = (m * y) * (y * y);
+  ax = fmaf(w, dx, ax);
+  ay = fmaf(w, dy, ay);
+  az = fmaf(w, dz, az);
+}
+
+// One source j against target k for the VJP (row formulation):
+//   g += s^-3/2 (h + t e),  t = -3 (e.h) / s,   dm += (gbar_j . e) s^-3/2
+// with e = x_j - x_k and h = m_k gbar_j - m_j gbar_k, formed as
+// fma(m_k, gbar_j, -(m_j gbar_k)).  For the self pair j == k that h is not
+// zero but the exact rounding error delta of m_k gbar_k, and since e = 0 the
+// pair adds exactly fma(y3_self, delta, g): see self_pair_term, which the
+// kernel subtracts afterwards so the self pair contributes nothing.
+template <typename T>
+__device__ __forceinline__ void vjp_pair(T ex, T ey, T ez, T mj, T gjx, T gjy,
+                                         T gjz, T mk, T gkx, T gky, T gkz,
+                                         T eps2, T &gx, T &gy, T &gz, T &dm) {
+  T s = fma(ex, ex, eps2);
+  s = fma(ey, ey, s);
+  s = fma(ez, ez, s);
+  T y;
+  if constexpr (sizeof(T) == 8) y = rsqrt_f64(s); else y = rsqrt_f32(s);
+  const T y2 = y * y;
+  const T y3 = y2 * y;
+  const T hx = fma(mk, gjx, -(mj * gkx));
+  const T hy = fma(mk, gjy, -(mj * gky));
+  const T hz = fma(mk, gjz, -(mj * gkz));
+  const T eh = fma(ez, hz, fma(ey, hy, ex * hx));
+  const T ge = fma(gjz, ez, fma(gjy, ey, gjx * ex));
+  dm = fma(ge, y3, dm);
+  const T t = (y2 * T(-3)) * eh;
+  gx = fma(y3, fma(t, ex, hx), gx);
+  gy = fma(y3, fma(t, ey, hy), gy);
+  gz = fma(y3, fma(t, ez, hz), gz);
+}
+
+// What vjp_pair adds to g for the self pair j == k (e = 0, s = eps^2): the
+// same y3 and h operations, evaluated once per target.  The product is
+// rounded like the pair's own fma(y3, delta, 0) (exact for FP32 operands);
+// contraction is off so the caller's subtraction cannot absorb it into an
+// FMA, which would leave the product's rounding error behind.
+template <typename T>
+__device__ __forceinline__ double self_pair_term(T mk, T gk, T eps2) {
+#pragma clang fp contract(off)
+  T y;
+  if constexpr (sizeof(T) == 8) y = rsqrt_f64(eps2); else y = rsqrt_f32(eps2);
+  const T y3 = (y * y) * y;
+  const T delta = fma(mk, gk, -(mk * gk));
+  return double(y3) * double(delta);
+}
+
+// ------------------------------------------------------ source tile layout --
+
+template <int PREC> struct Src;
+template <> struct Src<NBODY_FP64> { double x, y, z, m; };
+template <> struct Src<NBODY_MIXED> { float x, y, z, m; };
+template <> struct Src<NBODY_MIXED_D64> { double x, y, z; float m, pad; };
+
+template <int PREC>
+__device__ __forceinline__ Src<PREC> load_src(const double *__restrict__ pos,
+                                              const double *__restrict__ mass,
+                                              int n, int j, bool valid) {
+  Src<PREC> b{};
+  if (valid) {
+    b.x = pos[j];
+    b.y = pos[n + j];
+    b.z = pos[2 * n + j];
+    b.m = mass[j];   // rounds to FP32 in the mixed modes
+  }
+  return b;
+}
+
+template <int PREC> struct VSrc;
+template <> struct VSrc<NBODY_FP64> { double x, y, z, m, gx, gy, gz, pad; };
+template <> struct VSrc<NBODY_MIXED> { float x, y, z, m, gx, gy, gz, pad; };
+template <> struct VSrc<NBODY_MIXED_D64> {
+  double x, y, z;
+  float m, gx, gy, gz, pad0, pad1;
+};
+
+// Coordinate type of a target body and of its pair difference.
+template <int PREC> struct Coord { using T = double; using D = double; };
+template <> struct Coord<NBODY_MIXED> { using T = float; using D = float; };
+template <> struct Coord<NBODY_MIXED_D64> { using T = double; using D = float; };
+
+// Sum over the L consecutive lanes that share a target (L a power of two
+// dividing the wave size) by an xor butterfly: every stage adds the same two
+// values in both partner lanes, so all L lanes end with the bitwise same
+// total, in an order fixed by L alone.
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int m = 1; m < L; m <<= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+inline dim3 grid_body(int n, int ncomp) {
+  return dim3(unsigned((size_t(ncomp) * n + kBodyThreads - 1) / kBodyThreads));
+}
+
+}  // namespace
+}  // namespace nbody

@@ -50,6 +50,19 @@ hipError_t launch_vjp(const Plan &pl, int precision, int n, int row0, int nt,
                       double *boxes, double eps2, double scale, double *out_x,
                       double *out_m, size_t split_stride, hipStream_t st);
 
+// The NBODY_MIXED_NF / NBODY_MIXED_NF64 (near64) forms of launch_accel and
+// launch_vjp: fill the box scratch, then run the near / far kernel.
+hipError_t launch_accel_nf(const Plan &pl, int n, int row0, int nt,
+                           const double *pos, const double *mass,
+                           double *boxes, double eps2, double scale,
+                           double *out, size_t stride, bool near64,
+                           hipStream_t st);
+hipError_t launch_vjp_nf(const Plan &pl, int n, int row0, int nt,
+                         const double *pos, const double *mass,
+                         const double *gacc, double *boxes, double eps2,
+                         double scale, double *ox, double *om, size_t stride,
+                         bool near64, hipStream_t st);
+
 // Doubles of bounding-box scratch an NBODY_MIXED_NF launch of `kind` with
 // lanes-per-target L needs for nt targets against n sources.
 size_t near_far_box_doubles(KernelKind kind, int L, int64_t n, int64_t nt);

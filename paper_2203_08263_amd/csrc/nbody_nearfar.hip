@@ -1,0 +1,755 @@
+// gfx950 kernels of the near / far precision modes (NBODY_MIXED_NF and
+// NBODY_MIXED_NF64) and of the Morton (Z-order) sort that puts bodies in the
+// spatial order those modes are fast in.
+#include "nbody_device.h"
+
+namespace nbody {
+namespace {
+
+constexpr int kBodyThreadsSort = 256;
+
+// ------------------------------------------------- near / far (mixed NF) --
+//
+// NBODY_MIXED_NF chooses the pair arithmetic per run of sources that one
+// FP32 chunk sum covers (C consecutive entries per lane, C*L sources) and per
+// wave:
+//  - far runs: coordinates relative to the centre c of the workgroup's
+//    target bounding box (half-diagonal b), x - c taken in FP64 and rounded
+//    once to FP32, then the FP32 pair arithmetic of NBODY_MIXED.  A run is far
+//    for a wave when the gap between the run's bounding box and the bounding
+//    box of the wave's own targets exceeds kappa b, so every such pair has
+//    |d| > kappa b, and the coordinate error is at most
+//    u32 (|x_j - c| + |x_i - c| + |d|) <= u32 (2 |d| + 2 b) < (2 + 2/kappa) u32 |d|
+//    (kappa = 1/2: below 6 u32 |d|, the order of one rounding of d itself);
+//  - near runs: the NBODY_MIXED_D64 arithmetic (difference in FP64, rounded
+//    once to FP32), which keeps the close pairs -- whose errors dominate --
+//    as accurate as that mode; or, for NBODY_MIXED_NF64 (NEAR64), the FP64
+//    pair added straight into the FP64 sums, so the close pairs carry FP64
+//    rounding only.
+// Both forms of every source are staged in LDS; the choice is uniform over
+// each wave (no divergence) and depends only on positions, so results stay
+// deterministic.  All boxes (source runs, the targets of each wave and of
+// each workgroup) come from group_box_kernel, launched just before the
+// all-pairs kernel, so the kernel itself only reads them.  With bodies in a
+// spatial order
+// (nbody_morton_sort) most runs are far and the kernel runs close to the
+// NBODY_MIXED rate; in a random order every run is near and the results are
+// bitwise those of NBODY_MIXED_D64.
+
+constexpr double kNearFarKappa2 = 0.25;  // kappa = 1/2
+
+struct Box {
+  double lo[3], hi[3];
+};
+
+// Minimum over the lanes of each aligned group of `width` lanes (a power of
+// two up to 64) of the 6 values {x, y, z, -x, -y, -z}.
+__device__ __forceinline__ void group_min6(double v[6], int width) {
+  for (int m = 1; m < width; m <<= 1) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = fmin(v[c], __shfl_xor(v[c], m));
+  }
+}
+
+__device__ __forceinline__ void box_init6(double v[6], bool ok, double x,
+                                          double y, double z) {
+  const double inf = __builtin_huge_val();
+  v[0] = ok ? x : inf;
+  v[1] = ok ? y : inf;
+  v[2] = ok ? z : inf;
+  v[3] = ok ? -x : inf;
+  v[4] = ok ? -y : inf;
+  v[5] = ok ? -z : inf;
+}
+
+// A value that is the same in every lane of the wave, moved to scalar
+// registers (readfirstlane of both halves).
+__device__ __forceinline__ double wave_uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane(int(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<unsigned int>(lo));
+}
+
+// Boxes of the groups of w consecutive bodies base .. base + count - 1 of a
+// [3][stride] position array, for up to three group widths wk (powers of two
+// in [4, 256]; 0 = unused): bk[g*6 + {0,1,2}] = min of x, y, z over group g,
+// bk[g*6 + {3,4,5}] = max, for every group that starts below count.
+// NaN coordinates are ignored (minNum).
+__global__ __launch_bounds__(kThreads) void group_box_kernel(
+    int stride, int base, int count, const double *__restrict__ pos, int w0,
+    double *__restrict__ b0, int w1, double *__restrict__ b1, int w2,
+    double *__restrict__ b2) {
+  __shared__ double red[4 * 6];
+  const int j = blockIdx.x * kThreads + threadIdx.x;
+  const bool ok = j < count;
+  double v[6];
+  box_init6(v, ok, ok ? pos[base + j] : 0.0, ok ? pos[stride + base + j] : 0.0,
+            ok ? pos[2 * stride + base + j] : 0.0);
+  auto emit = [&](int w, double *b) {
+    if ((threadIdx.x & (w - 1)) == 0 && j < count) {
+      double *o = b + size_t(j / w) * 6;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        o[c] = v[c];
+        o[3 + c] = -v[3 + c];
+      }
+    }
+  };
+  for (int m = 1; m < 64; m <<= 1) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = fmin(v[c], __shfl_xor(v[c], m));
+    if (w0 == 2 * m) emit(w0, b0);
+    if (w1 == 2 * m) emit(w1, b1);
+    if (w2 == 2 * m) emit(w2, b2);
+  }
+  if (w0 > 64 || w1 > 64 || w2 > 64) {  // uniform: kernel arguments
+    const int wv = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) red[wv * 6 + c] = v[c];
+    }
+    __syncthreads();
+    for (int w = 128; w <= kThreads; w <<= 1) {
+      if ((threadIdx.x & (w - 1)) == 0) {
+        double u[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) u[c] = red[wv * 6 + c];
+        for (int k = 1; k < w / 64; ++k) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) u[c] = fmin(u[c], red[(wv + k) * 6 + c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = u[c];
+      }
+      if (w0 == w) emit(w0, b0);
+      if (w1 == w) emit(w1, b1);
+      if (w2 == w) emit(w2, b2);
+    }
+  }
+}
+
+// Box g of a box array, in scalar registers (the index is uniform).
+__device__ __forceinline__ Box read_box(const double *__restrict__ b, int g) {
+  Box r;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    r.lo[c] = wave_uniform(b[size_t(g) * 6 + c]);
+    r.hi[c] = wave_uniform(b[size_t(g) * 6 + 3 + c]);
+  }
+  return r;
+}
+
+// Far / near decisions of the NR runs of one tile (first source jt) for the
+// calling thread's wave: bit r of the result is set when run r is far.  Lane
+// r of the wave evaluates run r (a box gap in FP64) and a ballot gathers the
+// bits, so the per-chunk test is a scalar bit test.  Runs entirely past jend
+// (tile padding) are near.
+template <int RUN>
+__device__ __forceinline__ uint64_t far_runs(const Box &wave, double thr2,
+                                             const double *__restrict__ boxes,
+                                             int jt, int jend) {
+  constexpr int NR = kThreads / RUN;
+  const int lane = threadIdx.x & 63;
+  const int rs = jt + lane * RUN;
+  bool far = false;
+  if (lane < NR && rs < jend) {
+    const double *sb = boxes + size_t(rs / RUN) * 6;
+    double gap2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double g =
+          fmax(0.0, fmax(sb[c] - wave.hi[c], wave.lo[c] - sb[3 + c]));
+      gap2 += g * g;
+    }
+    far = gap2 > thr2;
+  }
+  return __ballot(far);
+}
+
+// Centre and far threshold (kappa b)^2 of the workgroup's target box.
+__device__ __forceinline__ double far_frame(const Box &block, double c[3]) {
+  double b2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    c[k] = 0.5 * (block.lo[k] + block.hi[k]);
+    const double e = block.hi[k] - block.lo[k];
+    b2 += e * e;
+  }
+  return kNearFarKappa2 * 0.25 * b2;
+}
+
+// Box arrays of the near / far kernels: run boxes over all n sources (RUN
+// bodies each), wave boxes over the nt targets (64/L each) and workgroup
+// boxes over the targets (256/L each).
+struct NfBoxes {
+  const double *run;
+  const double *wave;
+  const double *block;
+};
+
+// The wave's and the workgroup's target boxes; a wave with no valid target
+// (tail of the last workgroup) gets an empty box, so every run is far for it.
+template <int L>
+__device__ __forceinline__ void target_boxes(const NfBoxes &bx, int nt,
+                                             Box &wave, Box &block) {
+  constexpr int GW = 64 / L;
+  // wave index, uniform across the wave (scalar registers and branches)
+  const int wg = __builtin_amdgcn_readfirstlane(
+      int(blockIdx.x) * (kThreads / 64) + int(threadIdx.x) / 64);
+  const bool has = wg * GW < nt;
+  block = read_box(bx.block, blockIdx.x);
+  wave = read_box(bx.wave, has ? wg : 0);  // box 0 always exists
+  const double inf = __builtin_huge_val();
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    wave.lo[c] = has ? wave.lo[c] : inf;
+    wave.hi[c] = has ? wave.hi[c] : -inf;
+  }
+}
+
+template <int L, bool NEAR64>
+__global__ __launch_bounds__(kThreads) void accel_nf_kernel(
+    int n, int row0, int nt, const double *__restrict__ pos,
+    const double *__restrict__ mass, NfBoxes bx, double eps2d, double scale,
+    int jchunk, double *__restrict__ out, size_t split_stride) {
+  constexpr int G = kThreads / L;
+  constexpr int PER = kThreads / L;
+  constexpr int C = PER < kChunk ? PER : kChunk;
+  constexpr int RUN = C * L;  // sources of one chunk run (box granularity)
+  using NearSrc = Src<NEAR64 ? NBODY_FP64 : NBODY_MIXED_D64>;
+  __shared__ NearSrc near_tile[kThreads];
+  __shared__ Src<NBODY_MIXED> far_tile[kThreads];
+
+  const int tid = threadIdx.x;
+  const int g = tid / L, q = tid % L;
+  const int i = blockIdx.x * G + g;
+  const int jbeg = blockIdx.y * jchunk;
+  const int jend = min(n, jbeg + jchunk);
+  const bool ok = i < nt;
+  const int gi = row0 + i;
+  const double xi = ok ? pos[gi] : 0.0;
+  const double yi = ok ? pos[n + gi] : 0.0;
+  const double zi = ok ? pos[2 * n + gi] : 0.0;
+  Box wave, block;
+  target_boxes<L>(bx, nt, wave, block);
+  double c[3];
+  const double thr2 = far_frame(block, c);
+  const float xr = float(xi - c[0]);
+  const float yr = float(yi - c[1]);
+  const float zr = float(zi - c[2]);
+  const float eps2 = float(eps2d);
+  double ax = 0.0, ay = 0.0, az = 0.0;
+
+  for (int jt = jbeg; jt < jend; jt += kThreads) {
+    const int j = jt + tid;
+    const bool valid = j < jend;
+    const double xj = valid ? pos[j] : 0.0;
+    const double yj = valid ? pos[n + j] : 0.0;
+    const double zj = valid ? pos[2 * n + j] : 0.0;
+    const double mj64 = valid ? mass[j] : 0.0;
+    const float mj = float(mj64);
+    NearSrc bn{};
+    bn.x = xj;
+    bn.y = yj;
+    bn.z = zj;
+    if constexpr (NEAR64) bn.m = mj64; else bn.m = mj;
+    Src<NBODY_MIXED> bf{};
+    if (valid) {
+      bf.x = float(xj - c[0]);
+      bf.y = float(yj - c[1]);
+      bf.z = float(zj - c[2]);
+      bf.m = mj;
+    }
+    const uint64_t far_mask = far_runs<RUN>(wave, thr2, bx.run, jt, jend);
+    __syncthreads();  // previous tile fully consumed
+    near_tile[tid] = bn;
+    far_tile[tid] = bf;
+    __syncthreads();
+
+    for (int u0 = 0; u0 < PER; u0 += C) {
+      const bool far = (far_mask >> (u0 / C)) & 1u;  // run u0 / C of the tile
+      if (NEAR64 && !far) {
+#pragma unroll 4
+        for (int u = 0; u < C; ++u) {
+          const NearSrc s = near_tile[(u0 + u) * L + q];
+          pair_f64(s.x - xi, s.y - yi, s.z - zi, double(s.m), eps2d, ax, ay, az);
+        }
+        continue;
+      }
+      float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+      if (far) {
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+          const Src<NBODY_MIXED> s = far_tile[(u0 + u) * L + q];
+          pair_f32(s.x - xr, s.y - yr, s.z - zr, s.m, eps2, fx, fy, fz);
+        }
+      } else if constexpr (!NEAR64) {
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+          const NearSrc s = near_tile[(u0 + u) * L + q];
+          pair_f32(float(s.x - xi), float(s.y - yi), float(s.z - zi), float(s.m),
+                   eps2, fx, fy, fz);
+        }
+      }
+      ax += double(fx);
+      ay += double(fy);
+      az += double(fz);
+    }
+  }
+
+  double *o = out + size_t(blockIdx.y) * split_stride;
+  const double sx = group_sum<L>(ax);
+  const double sy = group_sum<L>(ay);
+  const double sz = group_sum<L>(az);
+  if (q == 0 && ok) {
+    o[i] = scale * sx;
+    o[nt + i] = scale * sy;
+    o[2 * nt + i] = scale * sz;
+  }
+}
+
+template <int L, bool NEAR64>
+__global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
+    int n, int row0, int nt, const double *__restrict__ pos,
+    const double *__restrict__ mass, const double *__restrict__ gacc,
+    NfBoxes bx, double eps2d, double scale, int jchunk,
+    double *__restrict__ out_x, double *__restrict__ out_m,
+    size_t split_stride) {
+  constexpr int G = kThreads / L;
+  constexpr int PER = kThreads / L;
+  constexpr int C = PER < kVjpChunk ? PER : kVjpChunk;
+  constexpr int RUN = C * L;
+  using NearSrc = VSrc<NEAR64 ? NBODY_FP64 : NBODY_MIXED_D64>;
+  __shared__ NearSrc near_tile[kThreads];
+  __shared__ VSrc<NBODY_MIXED> far_tile[kThreads];
+
+  const int tid = threadIdx.x;
+  const int g = tid / L, q = tid % L;
+  const int k = blockIdx.x * G + g;
+  const int jbeg = blockIdx.y * jchunk;
+  const int jend = min(n, jbeg + jchunk);
+  const bool ok = k < nt;
+  const int gk = row0 + k;
+  const double xk = ok ? pos[gk] : 0.0;
+  const double yk = ok ? pos[n + gk] : 0.0;
+  const double zk = ok ? pos[2 * n + gk] : 0.0;
+  const double mk64 = ok ? mass[gk] : 0.0;
+  const double gkx64 = ok ? gacc[gk] : 0.0;
+  const double gky64 = ok ? gacc[n + gk] : 0.0;
+  const double gkz64 = ok ? gacc[2 * n + gk] : 0.0;
+  const float mk = float(mk64);
+  const float gkx = float(gkx64);
+  const float gky = float(gky64);
+  const float gkz = float(gkz64);
+  Box wave, block;
+  target_boxes<L>(bx, nt, wave, block);
+  double c[3];
+  const double thr2 = far_frame(block, c);
+  const float xr = float(xk - c[0]);
+  const float yr = float(yk - c[1]);
+  const float zr = float(zk - c[2]);
+  const float eps2 = float(eps2d);
+  double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
+
+  for (int jt = jbeg; jt < jend; jt += kThreads) {
+    const int j = jt + tid;
+    const bool valid = j < jend;
+    const double xj = valid ? pos[j] : 0.0;
+    const double yj = valid ? pos[n + j] : 0.0;
+    const double zj = valid ? pos[2 * n + j] : 0.0;
+    const double mj64 = valid ? mass[j] : 0.0;
+    const double gjx64 = valid ? gacc[j] : 0.0;
+    const double gjy64 = valid ? gacc[n + j] : 0.0;
+    const double gjz64 = valid ? gacc[2 * n + j] : 0.0;
+    const float mj = float(mj64);
+    const float gjx = float(gjx64);
+    const float gjy = float(gjy64);
+    const float gjz = float(gjz64);
+    NearSrc bn{};
+    bn.x = xj;
+    bn.y = yj;
+    bn.z = zj;
+    if constexpr (NEAR64) {
+      bn.m = mj64;
+      bn.gx = gjx64;
+      bn.gy = gjy64;
+      bn.gz = gjz64;
+    } else {
+      bn.m = mj;
+      bn.gx = gjx;
+      bn.gy = gjy;
+      bn.gz = gjz;
+    }
+    VSrc<NBODY_MIXED> bf{};
+    if (valid) {
+      bf.x = float(xj - c[0]);
+      bf.y = float(yj - c[1]);
+      bf.z = float(zj - c[2]);
+    }
+    bf.m = mj;
+    bf.gx = gjx;
+    bf.gy = gjy;
+    bf.gz = gjz;
+    const uint64_t far_mask = far_runs<RUN>(wave, thr2, bx.run, jt, jend);
+    __syncthreads();
+    near_tile[tid] = bn;
+    far_tile[tid] = bf;
+    __syncthreads();
+
+    for (int u0 = 0; u0 < PER; u0 += C) {
+      const bool far = (far_mask >> (u0 / C)) & 1u;
+      if (NEAR64 && !far) {
+#pragma unroll 2
+        for (int u = 0; u < C; ++u) {
+          const NearSrc s = near_tile[(u0 + u) * L + q];
+          vjp_pair<double>(s.x - xk, s.y - yk, s.z - zk, double(s.m),
+                           double(s.gx), double(s.gy), double(s.gz), mk64, gkx64,
+                           gky64, gkz64, eps2d, sx, sy, sz, sm);
+        }
+        continue;
+      }
+      float fx = 0.0f, fy = 0.0f, fz = 0.0f, fm = 0.0f;
+      if (far) {
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+          const VSrc<NBODY_MIXED> s = far_tile[(u0 + u) * L + q];
+          vjp_pair<float>(s.x - xr, s.y - yr, s.z - zr, s.m, s.gx, s.gy, s.gz,
+                          mk, gkx, gky, gkz, eps2, fx, fy, fz, fm);
+        }
+      } else if constexpr (!NEAR64) {
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+          const NearSrc s = near_tile[(u0 + u) * L + q];
+          vjp_pair<float>(float(s.x - xk), float(s.y - yk), float(s.z - zk),
+                          float(s.m), float(s.gx), float(s.gy), float(s.gz), mk,
+                          gkx, gky, gkz, eps2, fx, fy, fz, fm);
+        }
+      }
+      sx += double(fx);
+      sy += double(fy);
+      sz += double(fz);
+      sm += double(fm);
+    }
+  }
+
+  double *ox = out_x + size_t(blockIdx.y) * split_stride;
+  double *om = out_m + size_t(blockIdx.y) * split_stride;
+  double tx = group_sum<L>(sx);
+  double ty = group_sum<L>(sy);
+  double tz = group_sum<L>(sz);
+  const double tm = group_sum<L>(sm);
+  if (q == 0 && ok) {
+    if (gk >= jbeg && gk < jend) {  // this split holds the self pair (e = 0),
+      // always in a near run (its run box contains x_k, gap 0)
+      if constexpr (NEAR64) {
+        tx -= self_pair_term<double>(mk64, gkx64, eps2d);
+        ty -= self_pair_term<double>(mk64, gky64, eps2d);
+        tz -= self_pair_term<double>(mk64, gkz64, eps2d);
+      } else {
+        tx -= self_pair_term<float>(mk, gkx, eps2);
+        ty -= self_pair_term<float>(mk, gky, eps2);
+        tz -= self_pair_term<float>(mk, gkz, eps2);
+      }
+    }
+    ox[k] = scale * tx;
+    ox[nt + k] = scale * ty;
+    ox[2 * nt + k] = scale * tz;
+    om[k] = -scale * tm;
+  }
+}
+
+// Sources per near / far decision of each kernel at lanes-per-target L.
+constexpr int nf_run(KernelKind kind, int L) {
+  return (kThreads / L < (kind == kVjp ? kVjpChunk : kChunk)
+              ? kThreads / L
+              : (kind == kVjp ? kVjpChunk : kChunk)) *
+         L;
+}
+
+// ------------------------------------------------------ Morton (Z) order --
+//
+// Key of body i: its position quantised on a 1024^3 grid spanning the cube
+// [lo, lo + ext]^3 (lo the componentwise minimum, ext the largest extent),
+// q = min(1023, floor((x - lo) * (1024 / ext))) per axis (all FP64, no
+// contraction), bits interleaved x, y, z from the most significant down
+// (bit 3b+2 = bit b of qx, 3b+1 of qy, 3b of qz), then shifted above a 33-bit
+// body index: key = (morton << 33) | i.  Keys are unique, so ascending order
+// is the stable sort by Morton code.  Padding keys are all ones.
+
+constexpr int kMortonBits = 10;
+constexpr int kIndexBits = 33;
+constexpr int kSortChunk = 2048;  // keys per workgroup in the LDS stages
+
+// Reduce group boxes to the global box: gbox[0..2] = lo, gbox[3..5] = hi.
+__global__ __launch_bounds__(kThreads) void box_merge_kernel(
+    int ngroups, const double *__restrict__ boxes, double *__restrict__ gbox) {
+  __shared__ double red[4 * 6];
+  const double inf = __builtin_huge_val();
+  double v[6] = {inf, inf, inf, inf, inf, inf};
+  for (int t = threadIdx.x; t < ngroups; t += kThreads) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      v[c] = fmin(v[c], boxes[size_t(t) * 6 + c]);
+      v[3 + c] = fmin(v[3 + c], -boxes[size_t(t) * 6 + 3 + c]);
+    }
+  }
+  group_min6(v, 64);
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) red[w * 6 + c] = v[c];
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 6) {
+    double m = red[t];
+    for (int k = 1; k < kThreads / 64; ++k) m = fmin(m, red[k * 6 + t]);
+    gbox[t] = t < 3 ? m : -m;
+  }
+}
+
+__device__ __forceinline__ uint64_t quantise(double x, double lo, double sc) {
+#pragma clang fp contract(off)
+  const double v = floor((x - lo) * sc);
+  if (!(v > 0.0)) return 0;  // also NaN
+  return v >= 1023.0 ? 1023u : uint64_t(v);
+}
+
+__global__ __launch_bounds__(kThreads) void morton_key_kernel(
+    int n, int64_t npad, const double *__restrict__ pos,
+    const double *__restrict__ gbox, uint64_t *__restrict__ keys) {
+  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= npad) return;
+  if (i >= n) {
+    keys[i] = ~uint64_t(0);
+    return;
+  }
+  const double ext = fmax(gbox[3] - gbox[0], fmax(gbox[4] - gbox[1], gbox[5] - gbox[2]));
+  const double sc = ext > 0.0 ? 1024.0 / ext : 0.0;
+  const uint64_t qx = quantise(pos[i], gbox[0], sc);
+  const uint64_t qy = quantise(pos[n + i], gbox[1], sc);
+  const uint64_t qz = quantise(pos[2 * n + i], gbox[2], sc);
+  uint64_t m = 0;
+#pragma unroll
+  for (int b = 0; b < kMortonBits; ++b) {
+    m |= ((qx >> b) & 1u) << (3 * b + 2);
+    m |= ((qy >> b) & 1u) << (3 * b + 1);
+    m |= ((qz >> b) & 1u) << (3 * b);
+  }
+  keys[i] = (m << kIndexBits) | uint64_t(i);
+}
+
+// Bitonic network on npad (a power of two) keys.  Pair (i, i + j) with
+// i & j == 0 is ordered ascending when i & k == 0, descending otherwise.
+__device__ __forceinline__ void cmp_swap(uint64_t &a, uint64_t &b, bool asc) {
+  if ((a > b) == asc) {
+    const uint64_t t = a;
+    a = b;
+    b = t;
+  }
+}
+
+// Stages k = 2 .. chunk (each chunk of `chunk` keys fully sorted, direction
+// by the global index) when kmin == 2; otherwise the j < chunk steps of stage
+// k = kmin.
+__global__ __launch_bounds__(kThreads) void bitonic_lds_kernel(
+    uint64_t *__restrict__ keys, int chunk, int64_t kmin) {
+  __shared__ uint64_t s[kSortChunk];
+  const int64_t base = int64_t(blockIdx.x) * chunk;
+  for (int e = threadIdx.x; e < chunk; e += kThreads) s[e] = keys[base + e];
+  __syncthreads();
+  const int64_t kfirst = kmin, klast = kmin == 2 ? chunk : kmin;
+  for (int64_t k = kfirst; k <= klast; k <<= 1) {
+    for (int j = int((k < chunk ? k : int64_t(chunk)) >> 1); j > 0; j >>= 1) {
+      for (int p = threadIdx.x; p < chunk / 2; p += kThreads) {
+        const int i = 2 * j * (p / j) + (p % j);
+        const bool asc = ((base + i) & k) == 0;
+        uint64_t a = s[i], b = s[i + j];
+        cmp_swap(a, b, asc);
+        s[i] = a;
+        s[i + j] = b;
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = threadIdx.x; e < chunk; e += kThreads) keys[base + e] = s[e];
+}
+
+// One global step (stride j >= chunk) of stage k.
+__global__ __launch_bounds__(kThreads) void bitonic_step_kernel(
+    uint64_t *__restrict__ keys, int64_t npad, int64_t j, int64_t k) {
+  const int64_t p = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (p >= npad / 2) return;
+  const int64_t i = 2 * j * (p / j) + (p % j);
+  uint64_t a = keys[i], b = keys[i + j];
+  cmp_swap(a, b, (i & k) == 0);
+  keys[i] = a;
+  keys[i + j] = b;
+}
+
+// perm[r] = index of the body at sorted position r; gather the state.
+__global__ __launch_bounds__(kBodyThreadsSort) void morton_gather_kernel(
+    int n, const uint64_t *__restrict__ keys, const double *__restrict__ pos,
+    const double *__restrict__ vel, const double *__restrict__ mass,
+    int64_t *__restrict__ perm, double *__restrict__ pos_out,
+    double *__restrict__ vel_out, double *__restrict__ mass_out) {
+  const int r = blockIdx.x * kBodyThreadsSort + threadIdx.x;
+  if (r >= n) return;
+  int64_t src = int64_t(keys[r] & ((uint64_t(1) << kIndexBits) - 1));
+  if (src >= n) src = n - 1;  // unreachable for a correct sort; keeps reads in bounds
+  perm[r] = src;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    pos_out[size_t(c) * n + r] = pos[size_t(c) * n + src];
+    if (vel) vel_out[size_t(c) * n + r] = vel[size_t(c) * n + src];
+  }
+  mass_out[r] = mass[src];
+}
+
+// Layout (in doubles) of the near / far box area of one all-pairs launch:
+// run boxes over the n sources, then wave and workgroup boxes over the nt
+// targets.
+struct NfLayout {
+  int run, gw, gb;
+  size_t off_wave, off_block, total;
+};
+
+NfLayout nf_layout(KernelKind kind, int L, int64_t n, int64_t nt) {
+  NfLayout l;
+  l.run = nf_run(kind, L);
+  l.gw = 64 / L;
+  l.gb = kThreads / L;
+  const size_t nr = size_t((n + l.run - 1) / l.run);
+  const size_t nw = size_t((nt + l.gw - 1) / l.gw);
+  const size_t nb = size_t((nt + l.gb - 1) / l.gb);
+  l.off_wave = nr * 6;
+  l.off_block = l.off_wave + nw * 6;
+  l.total = l.off_block + nb * 6;
+  return l;
+}
+
+// Fill the box area for a launch over targets row0 .. row0 + nt - 1: one
+// pass when the targets are all n bodies, otherwise one over the sources and
+// one over the target rows.
+hipError_t launch_nf_boxes(KernelKind kind, int L, int n, int row0, int nt,
+                           const double *pos, double *area, NfBoxes &bx,
+                           hipStream_t st) {
+  const NfLayout l = nf_layout(kind, L, n, nt);
+  double *rb = area, *wb = area + l.off_wave, *bb = area + l.off_block;
+  bx.run = rb;
+  bx.wave = wb;
+  bx.block = bb;
+  const unsigned sblocks = unsigned((n + kThreads - 1) / kThreads);
+  if (row0 == 0 && nt == n) {
+    group_box_kernel<<<sblocks, kThreads, 0, st>>>(n, 0, n, pos, l.run, rb, l.gw,
+                                                   wb, l.gb, bb);
+    return hipGetLastError();
+  }
+  group_box_kernel<<<sblocks, kThreads, 0, st>>>(n, 0, n, pos, l.run, rb, 0,
+                                                 nullptr, 0, nullptr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned tblocks = unsigned((nt + kThreads - 1) / kThreads);
+  group_box_kernel<<<tblocks, kThreads, 0, st>>>(n, row0, nt, pos, l.gw, wb,
+                                                 l.gb, bb, 0, nullptr);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_accel_nf(const Plan &pl, int n, int row0, int nt,
+                           const double *pos, const double *mass,
+                           double *boxes, double eps2, double scale,
+                           double *out, size_t stride, bool near64,
+                           hipStream_t st) {
+  if (pl.R != 1) return hipErrorInvalidValue;
+  NfBoxes bx;
+  const hipError_t e = launch_nf_boxes(kAccel, pl.L, n, row0, nt, pos, boxes, bx, st);
+  if (e != hipSuccess) return e;
+  const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
+  const int jc = int(pl.jchunk);
+#define NBODY_ACCEL_NF(L_, N64_)                                                 \
+  accel_nf_kernel<L_, N64_><<<grid, kThreads, 0, st>>>(n, row0, nt, pos, mass,   \
+                                                       bx, eps2, scale, jc, out, \
+                                                       stride)
+  if (pl.L == 1) { if (near64) NBODY_ACCEL_NF(1, true); else NBODY_ACCEL_NF(1, false); }
+  else if (pl.L == 4) { if (near64) NBODY_ACCEL_NF(4, true); else NBODY_ACCEL_NF(4, false); }
+  else if (pl.L == 16) { if (near64) NBODY_ACCEL_NF(16, true); else NBODY_ACCEL_NF(16, false); }
+  else return hipErrorInvalidValue;
+#undef NBODY_ACCEL_NF
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp_nf(const Plan &pl, int n, int row0, int nt,
+                         const double *pos, const double *mass,
+                         const double *gacc, double *boxes, double eps2,
+                         double scale, double *ox, double *om, size_t stride,
+                         bool near64, hipStream_t st) {
+  if (pl.R != 1) return hipErrorInvalidValue;
+  NfBoxes bx;
+  const hipError_t e = launch_nf_boxes(kVjp, pl.L, n, row0, nt, pos, boxes, bx, st);
+  if (e != hipSuccess) return e;
+  const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
+  const int jc = int(pl.jchunk);
+#define NBODY_VJP_NF(L_, N64_)                                                   \
+  vjp_nf_kernel<L_, N64_><<<grid, kThreads, 0, st>>>(n, row0, nt, pos, mass,     \
+                                                     gacc, bx, eps2, scale, jc,  \
+                                                     ox, om, stride)
+  if (pl.L == 1) { if (near64) NBODY_VJP_NF(1, true); else NBODY_VJP_NF(1, false); }
+  else if (pl.L == 4) { if (near64) NBODY_VJP_NF(4, true); else NBODY_VJP_NF(4, false); }
+  else if (pl.L == 16) { if (near64) NBODY_VJP_NF(16, true); else NBODY_VJP_NF(16, false); }
+  else return hipErrorInvalidValue;
+#undef NBODY_VJP_NF
+  return hipGetLastError();
+}
+
+size_t near_far_box_doubles(KernelKind kind, int L, int64_t n, int64_t nt) {
+  return nf_layout(kind, L, n, nt).total;
+}
+
+int64_t morton_padded(int64_t n) {
+  int64_t p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+hipError_t launch_morton_sort(int n, const double *pos, const double *vel,
+                              const double *mass, int64_t *perm,
+                              double *pos_out, double *vel_out,
+                              double *mass_out, double *boxes, double *gbox,
+                              uint64_t *keys, hipStream_t st) {
+  const int ntiles = (n + kThreads - 1) / kThreads;
+  const int64_t npad = morton_padded(n);
+  group_box_kernel<<<unsigned(ntiles), kThreads, 0, st>>>(
+      n, 0, n, pos, kThreads, boxes, 0, nullptr, 0, nullptr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  box_merge_kernel<<<1, kThreads, 0, st>>>(ntiles, boxes, gbox);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  morton_key_kernel<<<unsigned((npad + kThreads - 1) / kThreads), kThreads, 0,
+                      st>>>(n, npad, pos, gbox, keys);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (npad > 1) {
+    const int chunk = int(npad < kSortChunk ? npad : kSortChunk);
+    const unsigned nchunks = unsigned(npad / chunk);
+    bitonic_lds_kernel<<<nchunks, kThreads, 0, st>>>(keys, chunk, 2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const unsigned step_blocks = unsigned((npad / 2 + kThreads - 1) / kThreads);
+    for (int64_t k = int64_t(chunk) * 2; k <= npad; k <<= 1) {
+      for (int64_t j = k >> 1; j >= chunk; j >>= 1) {
+        bitonic_step_kernel<<<step_blocks, kThreads, 0, st>>>(keys, npad, j, k);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+      bitonic_lds_kernel<<<nchunks, kThreads, 0, st>>>(keys, chunk, k);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  morton_gather_kernel<<<unsigned((n + kBodyThreadsSort - 1) / kBodyThreadsSort),
+                         kBodyThreadsSort, 0, st>>>(n, keys, pos, vel, mass, perm,
+                                                    pos_out, vel_out, mass_out);
+  return hipGetLastError();
+}
+
+}  // namespace nbody
