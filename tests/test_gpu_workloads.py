@@ -279,3 +279,31 @@ def test_plummer262144_accel_vjp(B, dev, oracle, prec):
     bx, bm = _tol.vjp_bound(pos, mass, g, w.G, w.eps, prec, brow)
     _check_bound(gx[:, sel], rx[:, sel], bx, "dL/dx")
     assert np.all(np.abs(gm[sel] - rm[sel]) <= bm), "dL/dm"
+
+
+# ------------------------------- largest size in the suite: N = 2^20 + 5 --
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_large_ragged_system_sampled_rows(B, dev, oracle, prec):
+    # 1048581 bodies (a ragged last tile; 1.1e12 pairs per call): accel and
+    # VJP on 128 seeded rows against the oracle's rows, every row of the
+    # output finite
+    n = (1 << 20) + 5
+    say("large", n, prec)
+    pos, _, mass = inputs.uniform_cube(n, 3001)
+    g = inputs.upstream_normal(n, 3002)
+    rows = inputs.subset_rows(n, 128, 3003)
+    rows[-1] = n - 1                      # include the very last body
+    rows = np.unique(rows)
+    P, M, Gt = T(pos, dev), T(mass, dev), T(g, dev)
+    a = N(B.nbody_accel(P, M, 1.0, 1e-3, prec))
+    assert np.isfinite(a).all()
+    _check_bound(a[:, rows], oracle.accel_rows(pos, mass, 1.0, 1e-3, rows),
+                 _tol.accel_bound(pos, mass, 1.0, 1e-3, prec, rows), "accel")
+    gx, gm = B.nbody_accel_vjp(P, M, Gt, 1.0, 1e-3, prec)
+    gx, gm = N(gx), N(gm)
+    assert np.isfinite(gx).all() and np.isfinite(gm).all()
+    rx, rm = oracle.accel_vjp_rows(pos, mass, g, 1.0, 1e-3, rows)
+    bx, bm = _tol.vjp_bound(pos, mass, g, 1.0, 1e-3, prec, rows)
+    _check_bound(gx[:, rows], rx, bx, "dL/dx")
+    assert np.all(np.abs(gm[rows] - rm) <= bm), "dL/dm"
