@@ -343,6 +343,59 @@ def shape_legs(torch, B, inputs):
     return out
 
 
+def adjoint_leg(torch, B, inputs):
+    """The forward + adjoint configuration: N = 8192 uniform cube, 50 KDK
+    steps with a checkpoint every 10, then the reverse sweep (which
+    recomputes each segment).  Step-level t_bwd / t_fwd per precision."""
+    dev = torch.device("cuda:0")
+    w = inputs.WORKLOADS["cube8192_adjoint"]
+    T = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa
+    pos, vel, mass = w.initial_state()
+    P0, V0, M = T(pos), T(vel), T(mass)
+    GX0 = T(inputs.upstream_normal(w.n, w.seed + 500))
+    P, V, A = torch.empty_like(P0), torch.empty_like(P0), torch.empty_like(P0)
+    GX, GV, GM = torch.empty_like(P0), torch.empty_like(P0), torch.empty_like(M)
+    K = w.ckpt_every
+    CK = torch.empty(B.nbody_checkpoint_bytes(w.n, w.steps, K) // 8, dtype=torch.float64,
+                     device=dev)
+    out = {"workload": "cube8192_adjoint: N=%d, %d KDK steps, checkpoint every %d"
+                       % (w.n, w.steps, K)}
+    for p in ("mixed", "fp64"):
+        ws = torch.empty(max(B.nbody_workspace_bytes(B.NBODY_OP_STEP, w.n, w.steps, K, p),
+                             B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, w.n,
+                                                     w.steps, K, p)),
+                         dtype=torch.uint8, device=dev)
+
+        def fwd():
+            P.copy_(P0)
+            V.copy_(V0)
+            B.nbody_step(P, V, A, M, w.G, w.eps, w.dt, w.steps, p, ckpt=CK,
+                         ckpt_every=K, workspace=ws)
+
+        def bwd():
+            GX.copy_(GX0)
+            GV.zero_()
+            B.nbody_step_adjoint(CK, M, GX, GV, w.G, w.eps, w.dt, w.steps, K, p,
+                                 gmass=GM, workspace=ws)
+        warm(torch, lambda: (fwd(), bwd()))
+        times = []
+        for fn in (fwd, bwd):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            fwd()   # the adjoint reads this forward's checkpoints
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(3):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 3)
+        tf, tb = times
+        out[p] = {"fwd_ms": round(tf, 4), "bwd_ms": round(tb, 4),
+                  "bwd_over_fwd": round(tb / tf, 3),
+                  "fwd_adj_G_int_s": round(float(w.n) * w.n * w.steps / ((tf + tb) * 1e-3) / 1e9, 1)}
+    return out
+
+
 def small_rollout_leg(torch, B, inputs):
     """The launch-bound configuration: N = 1024, 100 FP64 KDK steps (two
     launches per step).  Timed eagerly and as a replayed HIP graph of the same
@@ -392,7 +445,7 @@ def small_rollout_leg(torch, B, inputs):
             "graph_G_int_s": round(pairs / (graph * 1e-3) / 1e9, 1)}
 
 
-def cpu_baseline(bench, p, gx_gpu, gv_gpu, gm_gpu, x_end, v_end):
+def cpu_baseline(bench, p, gx_gpu, gv_gpu, gm_gpu, x_end, v_end, finals=None):
     """The FP64 oracle on the host cores over the same workload (forward plus
     exact reverse sweep), and the stated errors of the GPU results."""
     import numpy as np
@@ -427,6 +480,11 @@ def cpu_baseline(bench, p, gx_gpu, gv_gpu, gm_gpu, x_end, v_end):
     e0 = sum(oracle.energy(pos, vel, mass, w.G, w.eps))
     e1 = sum(oracle.energy(x_end, v_end, mass, w.G, w.eps))
     err["energy_drift_%s_%dsteps" % (p, w.steps)] = float("%.3e" % (abs(e1 - e0) / abs(e0)))
+    # and of every precision's rollout (final states of the legs; bodies in
+    # Morton order for the near / far modes: the energy is order-independent)
+    for q, (xq, vq, mq) in (finals or {}).items():
+        eq = sum(oracle.energy(xq, vq, mq, w.G, w.eps))
+        err["energy_drift_%s_%dsteps" % (q, w.steps)] = float("%.3e" % (abs(eq - e0) / abs(e0)))
     rows = w.rows(2048)
     ref = oracle.accel_rows(pos, mass, w.G, w.eps, rows)
     for q in PRECS:
@@ -508,6 +566,7 @@ def main(argv=None):
     x_end, v_end = bench.P.cpu().numpy(), bench.V.cpu().numpy()
 
     legs = {}
+    finals = {}
     if not args.no_legs:
         for q in PRECS:
             warm(torch, lambda: bench.forward(q))
@@ -518,6 +577,9 @@ def main(argv=None):
                        "fwd_adj_G_int_s": round(n2s / (sms * 1e-3) / 1e9, 1),
                        "fwd_adj_ms": round(sms, 4),
                        "bwd_over_fwd": round((sms - fms) / fms, 3)}
+            # the forward of the last timed step left this precision's final state
+            finals[q] = (bench.P.cpu().numpy(), bench.V.cpu().numpy(),
+                         bench.state0(q)[2].cpu().numpy())
             log("bench: leg %s %s" % (q, legs[q]))
         # checkpoint interval: K = 1 stores every state (no recomputation),
         # K = steps keeps one record and recomputes the whole rollout
@@ -569,10 +631,11 @@ def main(argv=None):
         log("bench: kernel legs at N = 65536 and 262144")
         out["shapes"] = shape_legs(torch, B, inputs)
         out["shapes"]["cube1024_fp64_rollout"] = small_rollout_leg(torch, B, inputs)
+        out["shapes"]["cube8192_adjoint"] = adjoint_leg(torch, B, inputs)
         log("bench: shapes %s" % out["shapes"])
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (FP64 oracle on the host cores)")
-        base, err = cpu_baseline(bench, p, gx, gv, gm, x_end, v_end)
+        base, err = cpu_baseline(bench, p, gx, gv, gm, x_end, v_end, finals)
         out["cpu_baseline"] = base
         out["error"] = err
     else:
