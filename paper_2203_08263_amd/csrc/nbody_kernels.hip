@@ -533,12 +533,17 @@ Plan make_plan(KernelKind kind, int precision, int64_t nt, int64_t n) {
   // resident waves per SIMD, several rounds of them), reached with the
   // smallest lanes-per-target L in {1, 4, 16} that needs at most 64 source
   // splits, each at least one 256-body tile long.  Target blocks count the
-  // nt target rows, source splits the n source bodies.
+  // nt target rows, source splits the n source bodies.  NBODY_MIXED_NF64
+  // starts at L = 4: its near runs are FP64 pairs, and the finer target
+  // waves and source runs of L = 4 leave fewer pairs near (measured: +21 %
+  // forward at N = 65536, +8 % at 262144, equal at 16384; L = 16 is slower
+  // for both near / far modes).
   const int R = (precision == NBODY_FP64 && kind != kPotential) ? 2 : 1;
   const int64_t target = 8192, max_sj = 64;
   const int64_t ntiles = (n + kThreads - 1) / kThreads;
   Plan p{};
   for (int L : {1, 4, 16}) {
+    if (precision == NBODY_MIXED_NF64 && L < 4) continue;
     const int64_t per_block = int64_t(kThreads / L) * R;
     p.R = R;
     p.L = L;

@@ -285,10 +285,12 @@ def test_near_far_workspace_adds_box_scratch(B):
         # rows: boxes over all n sources plus the target rows' own
         r = B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, n, max(1, n // 8), 3)
         assert r > B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, n, max(1, n // 8), 1)
-        # the FP64-near variant needs exactly the same scratch
+        # the FP64-near variant has boxes too (its plan may use more lanes
+        # per target, hence fewer splits and a different size)
         for op in (B.NBODY_OP_ACCEL, B.NBODY_OP_VJP, B.NBODY_OP_STEP):
-            assert (B.nbody_workspace_bytes(op, n, 10, 1, B.NBODY_MIXED_NF64)
-                    == B.nbody_workspace_bytes(op, n, 10, 1, B.NBODY_MIXED_NF))
+            nf64 = B.nbody_workspace_bytes(op, n, 10, 1, B.NBODY_MIXED_NF64)
+            assert 0 < nf64 and nf64 % 256 == 0
+            assert nf64 <= B.nbody_workspace_bytes(op, n, 10, 1, B.NBODY_MIXED) + most(n)
         # the potential of the diagnostics uses the D64 arithmetic, no boxes
         assert (B.nbody_workspace_bytes(B.NBODY_OP_DIAGNOSTICS, n, 0, 1, 3)
                 == B.nbody_workspace_bytes(B.NBODY_OP_DIAGNOSTICS, n, 0, 1, 2))
