@@ -118,6 +118,13 @@ def _check(rc: int):
                          lib.nbody_error_string(rc).decode())
 
 
+def _run(dev, fn, *args):
+    """Call a library entry point with the tensors' device current (the
+    library launches on the current HIP device) and check its status."""
+    with torch.cuda.device(dev):
+        _check(fn(*args))
+
+
 def _precision(p) -> int:
     if isinstance(p, str):
         if p not in PRECISIONS:
@@ -211,8 +218,8 @@ def nbody_accel(pos, mass, G=1.0, eps=1e-3, precision=NBODY_FP64, out=None,
     ws, wsb = _workspace(lib.nbody_workspace_bytes(NBODY_OP_ACCEL, n, 0, 1, prec),
                          dev, workspace)
     prm = _Params(G, eps, 0.0)
-    _check(lib.nbody_accel(n, _ptr(pos), _ptr(mass), _ptr(acc), ctypes.byref(prm),
-                           prec, _ptr(ws), wsb, _stream(dev)))
+    _run(dev, lib.nbody_accel, n, _ptr(pos), _ptr(mass), _ptr(acc), ctypes.byref(prm),
+         prec, _ptr(ws), wsb, _stream(dev))
     return acc
 
 
@@ -247,9 +254,9 @@ def nbody_step(pos, vel, acc, mass, G=1.0, eps=1e-3, dt=1e-3, steps=1,
                          dev, workspace)
     prm = _Params(G, eps, dt)
     flags = (NBODY_ACC_VALID if acc_valid else 0) | _integrator(integrator)
-    _check(lib.nbody_step(n, int(steps), _ptr(pos), _ptr(vel), _ptr(acc),
-                          _ptr(mass), ctypes.byref(prm), prec, flags, _ptr(ckpt),
-                          int(ckpt_every), _ptr(ws), wsb, _stream(dev)))
+    _run(dev, lib.nbody_step, n, int(steps), _ptr(pos), _ptr(vel), _ptr(acc),
+         _ptr(mass), ctypes.byref(prm), prec, flags, _ptr(ckpt),
+         int(ckpt_every), _ptr(ws), wsb, _stream(dev))
     return pos, vel, acc
 
 
@@ -270,9 +277,9 @@ def nbody_accel_vjp(pos, mass, gacc, G=1.0, eps=1e-3, precision=NBODY_FP64,
     ws, wsb = _workspace(lib.nbody_workspace_bytes(NBODY_OP_VJP, n, 0, 1, prec),
                          dev, workspace)
     prm = _Params(G, eps, 0.0)
-    _check(lib.nbody_accel_vjp(n, _ptr(pos), _ptr(mass), _ptr(gacc), _ptr(gpos),
-                               _ptr(gmass), ctypes.byref(prm), prec, _ptr(ws),
-                               wsb, _stream(dev)))
+    _run(dev, lib.nbody_accel_vjp, n, _ptr(pos), _ptr(mass), _ptr(gacc), _ptr(gpos),
+         _ptr(gmass), ctypes.byref(prm), prec, _ptr(ws),
+         wsb, _stream(dev))
     return gpos, gmass
 
 
@@ -302,11 +309,11 @@ def nbody_step_adjoint(ckpt, mass, gpos, gvel, G=1.0, eps=1e-3, dt=1e-3,
     ws, wsb = _workspace(lib.nbody_workspace_bytes(NBODY_OP_STEP_ADJOINT, n, steps,
                                                    ckpt_every, prec), dev, workspace)
     prm = _Params(G, eps, dt)
-    _check(lib.nbody_step_adjoint(n, int(steps), int(ckpt_every), _ptr(ckpt),
-                                  _ptr(mass), ctypes.byref(prm), prec,
-                                  _integrator(integrator), _ptr(gpos),
-                                  _ptr(gvel), _ptr(gacc_T), _ptr(gmass), _ptr(ws),
-                                  wsb, _stream(dev)))
+    _run(dev, lib.nbody_step_adjoint, n, int(steps), int(ckpt_every), _ptr(ckpt),
+         _ptr(mass), ctypes.byref(prm), prec,
+         _integrator(integrator), _ptr(gpos),
+         _ptr(gvel), _ptr(gacc_T), _ptr(gmass), _ptr(ws),
+         wsb, _stream(dev))
     return gpos, gvel, gmass
 
 
@@ -329,8 +336,8 @@ def nbody_diagnostics(pos, vel, mass, G=1.0, eps=1e-3, precision=NBODY_FP64,
     ws, wsb = _workspace(lib.nbody_workspace_bytes(NBODY_OP_DIAGNOSTICS, n, 0, 1, prec),
                          dev, workspace)
     prm = _Params(G, eps, 0.0)
-    _check(lib.nbody_diagnostics(n, _ptr(pos), _ptr(vel), _ptr(mass), ctypes.byref(prm),
-                                 prec, _ptr(out), _ptr(ws), wsb, _stream(dev)))
+    _run(dev, lib.nbody_diagnostics, n, _ptr(pos), _ptr(vel), _ptr(mass), ctypes.byref(prm),
+         prec, _ptr(out), _ptr(ws), wsb, _stream(dev))
     return out
 
 
@@ -355,9 +362,9 @@ def nbody_accel_rows(pos, mass, row_begin, row_count, G=1.0, eps=1e-3,
     ws, wsb = _workspace(lib.nbody_rows_workspace_bytes(NBODY_OP_ACCEL, n, rows,
                                                         prec), dev, workspace)
     prm = _Params(G, eps, 0.0)
-    _check(lib.nbody_accel_rows(n, int(row_begin), rows, _ptr(pos), _ptr(mass),
-                                _ptr(acc), ctypes.byref(prm), prec, _ptr(ws), wsb,
-                                _stream(dev)))
+    _run(dev, lib.nbody_accel_rows, n, int(row_begin), rows, _ptr(pos), _ptr(mass),
+         _ptr(acc), ctypes.byref(prm), prec, _ptr(ws), wsb,
+         _stream(dev))
     return acc
 
 
@@ -379,10 +386,10 @@ def nbody_accel_vjp_rows(pos, mass, gacc, row_begin, row_count, G=1.0, eps=1e-3,
     ws, wsb = _workspace(lib.nbody_rows_workspace_bytes(NBODY_OP_VJP, n, rows,
                                                         prec), dev, workspace)
     prm = _Params(G, eps, 0.0)
-    _check(lib.nbody_accel_vjp_rows(n, int(row_begin), rows, _ptr(pos), _ptr(mass),
-                                    _ptr(gacc), _ptr(gpos), _ptr(gmass),
-                                    ctypes.byref(prm), prec, _ptr(ws), wsb,
-                                    _stream(dev)))
+    _run(dev, lib.nbody_accel_vjp_rows, n, int(row_begin), rows, _ptr(pos), _ptr(mass),
+         _ptr(gacc), _ptr(gpos), _ptr(gmass),
+         ctypes.byref(prm), prec, _ptr(ws), wsb,
+         _stream(dev))
     return gpos, gmass
 
 
@@ -403,9 +410,9 @@ def nbody_morton_sort(pos, mass, vel=None, workspace=None):
     mass_out = torch.empty(n, dtype=torch.float64, device=dev)
     ws, wsb = _workspace(lib.nbody_workspace_bytes(NBODY_OP_MORTON_SORT, n, 0, 1, 0),
                          dev, workspace)
-    _check(lib.nbody_morton_sort(n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(perm),
-                                 _ptr(pos_out), _ptr(vel_out), _ptr(mass_out),
-                                 _ptr(ws), wsb, _stream(dev)))
+    _run(dev, lib.nbody_morton_sort, n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(perm),
+         _ptr(pos_out), _ptr(vel_out), _ptr(mass_out),
+         _ptr(ws), wsb, _stream(dev))
     return perm, pos_out, vel_out, mass_out
 
 
@@ -425,8 +432,8 @@ def nbody_accel_f32(pos, mass, G=1.0, eps=1e-3, out=None, workspace=None):
     ws, wsb = _workspace(lib.nbody_f32_workspace_bytes(NBODY_OP_ACCEL, n), dev,
                          workspace)
     prm = _Params(G, eps, 0.0)
-    _check(lib.nbody_accel_f32(n, _ptr(pos), _ptr(mass), _ptr(acc),
-                               ctypes.byref(prm), _ptr(ws), wsb, _stream(dev)))
+    _run(dev, lib.nbody_accel_f32, n, _ptr(pos), _ptr(mass), _ptr(acc),
+         ctypes.byref(prm), _ptr(ws), wsb, _stream(dev))
     return acc
 
 
@@ -443,7 +450,7 @@ def nbody_step_f32(pos, vel, acc, mass, G=1.0, eps=1e-3, dt=1e-3, steps=1,
                          workspace)
     prm = _Params(G, eps, dt)
     flags = (NBODY_ACC_VALID if acc_valid else 0) | _integrator(integrator)
-    _check(lib.nbody_step_f32(n, int(steps), _ptr(pos), _ptr(vel), _ptr(acc),
-                              _ptr(mass), ctypes.byref(prm), flags, _ptr(ws), wsb,
-                              _stream(dev)))
+    _run(dev, lib.nbody_step_f32, n, int(steps), _ptr(pos), _ptr(vel), _ptr(acc),
+         _ptr(mass), ctypes.byref(prm), flags, _ptr(ws), wsb,
+         _stream(dev))
     return pos, vel, acc
