@@ -215,3 +215,27 @@ def test_plummer262144_sorted_share(B, dev, oracle, prec):
     bx, bm = _tol.vjp_bound(pos, mass, g, w.G, w.eps, prec, rows)
     _check_bound(gx, rx, bx, "dL/dx")
     assert np.all(np.abs(gm - rm) <= bm), "dL/dm"
+
+
+# ----------------------------------------------------- the accuracy targets --
+
+@pytest.mark.parametrize("name,k", [("cube16384", None), ("plummer65536", 4096),
+                                    ("plummer262144_vjp", 1024)])
+def test_accuracy_targets(B, dev, oracle, name, k):
+    # the stated targets: FP64 accelerations within 1e-12 (max relative, per
+    # body) and a mixed mode within 1e-6 -- NBODY_MIXED_NF64 on the bodies in
+    # Morton order (all rows of the N = 16384 cube, seeded rows otherwise)
+    from paper_2203_08263_amd import metrics
+    w = inputs.WORKLOADS[name]
+    pos, _, mass = w.initial_state()
+    rows = np.arange(w.n) if k is None else w.rows(k)
+    a = N(B.nbody_accel(T(pos, dev), T(mass, dev), w.G, w.eps, "fp64"))[:, rows]
+    e64 = metrics.rel_errors(a, oracle.accel_rows(pos, mass, w.G, w.eps, rows))
+    o = oracle.morton_order(pos)
+    ps, ms = pos[:, o].copy(), mass[o].copy()
+    a = N(B.nbody_accel(T(ps, dev), T(ms, dev), w.G, w.eps, "mixed_nf64"))[:, rows]
+    e32 = metrics.rel_errors(a, oracle.accel_rows(ps, ms, w.G, w.eps, rows))
+    say("  %s: fp64 E_max %.2e, mixed_nf64 E_max %.2e E_norm %.2e"
+        % (name, e64["E_max"], e32["E_max"], e32["E_norm"]))
+    assert e64["E_max"] <= 1e-12
+    assert e32["E_max"] <= 1e-6
