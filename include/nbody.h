@@ -128,6 +128,11 @@ enum nbody_op {
 /* Largest supported body count. */
 #define NBODY_MAX_N ((int64_t)1 << 28)
 
+/* Largest supported step count of one nbody_step / nbody_step_adjoint call
+ * (larger counts, and checkpoint or workspace sizes beyond 2^62 bytes, are
+ * rejected as INVALID_ARGUMENT rather than overflowing a size). */
+#define NBODY_MAX_STEPS ((int64_t)1 << 40)
+
 /* Workspace (device scratch) bytes that `op` needs for these arguments; 0 if
  * none is needed, and (size_t)-1 if the arguments are invalid.  steps and
  * ckpt_every only matter for NBODY_OP_STEP_ADJOINT. */

@@ -79,6 +79,15 @@ constexpr size_t kAlign = 256;
 constexpr size_t kInvalid = (size_t)-1;
 
 size_t round_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+// a * b * elem bytes, or kInvalid when that exceeds 2^62 (no size_t wrap).
+size_t checked_bytes(int64_t a, int64_t b, int64_t elem) {
+  const unsigned __int128 v = (unsigned __int128)a * (unsigned __int128)b *
+                              (unsigned __int128)elem;
+  return v > ((unsigned __int128)1 << 62) ? kInvalid : size_t(v);
+}
+
+bool valid_steps(int64_t steps) { return steps >= 0 && steps <= NBODY_MAX_STEPS; }
 size_t dbytes(int64_t count) { return round_up(size_t(count) * sizeof(double)); }
 
 bool valid_precision(int p) {
@@ -182,8 +191,10 @@ size_t ws_part_adjoint(int64_t n, int prec) {
 }
 size_t ws_adjoint(int64_t n, int64_t steps, int64_t K, int prec) {
   const int64_t seg = std::min<int64_t>(K, std::max<int64_t>(steps, 1));
+  const size_t seg_bytes = checked_bytes(seg, 3 * n, sizeof(double));
+  if (seg_bytes == kInvalid) return kInvalid;
   // v, a, abar, segment positions, box scratch, partial sums
-  return 3 * dbytes(3 * n) + dbytes(seg * 3 * n) + box_bytes_adj(n, prec) +
+  return 3 * dbytes(3 * n) + round_up(seg_bytes) + box_bytes_adj(n, prec) +
          ws_part_adjoint(n, prec);
 }
 
@@ -294,7 +305,7 @@ size_t nbody_workspace_bytes(int op, int64_t n, int64_t steps,
     case NBODY_OP_STEP: return ws_step(n, precision);
     case NBODY_OP_VJP: return ws_vjp(n, precision);
     case NBODY_OP_STEP_ADJOINT:
-      if (steps < 0 || ckpt_every < 1) return kInvalid;
+      if (!valid_steps(steps) || ckpt_every < 1) return kInvalid;
       return ws_adjoint(n, steps, ckpt_every, precision);
     case NBODY_OP_DIAGNOSTICS: return ws_diag(n, precision);
     case NBODY_OP_MORTON_SORT: return ws_morton(n);
@@ -315,9 +326,9 @@ size_t nbody_rows_workspace_bytes(int op, int64_t n, int64_t row_count,
 }
 
 size_t nbody_checkpoint_bytes(int64_t n, int64_t steps, int64_t ckpt_every) {
-  if (n < 1 || n > NBODY_MAX_N || steps < 0 || ckpt_every < 1) return kInvalid;
-  return size_t(num_records(steps, ckpt_every)) * 9 * size_t(n) *
-         sizeof(double);
+  if (n < 1 || n > NBODY_MAX_N || !valid_steps(steps) || ckpt_every < 1)
+    return kInvalid;
+  return checked_bytes(num_records(steps, ckpt_every), 9 * n, sizeof(double));
 }
 
 int nbody_accel(int64_t n, const double *pos, const double *mass, double *acc,
@@ -425,9 +436,9 @@ int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
                int64_t ckpt_every, void *ws, size_t ws_bytes, void *stream) {
   int rc;
   if ((rc = check_common(n, p, precision, true))) return rc;
-  if (steps < 0)
-    return fail(NBODY_ERR_INVALID_ARGUMENT, "steps = %lld < 0",
-                (long long)steps);
+  if (!valid_steps(steps))
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "steps = %lld outside [0, %lld]",
+                (long long)steps, (long long)NBODY_MAX_STEPS);
   if (flags & ~(NBODY_ACC_VALID | NBODY_HALF_KICK_DRIFT))
     return fail(NBODY_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x",
                 flags & ~(NBODY_ACC_VALID | NBODY_HALF_KICK_DRIFT));
@@ -440,6 +451,10 @@ int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
                   "ckpt_every = %lld < 1 with a checkpoint buffer",
                   (long long)ckpt_every);
     if ((rc = check_ptr(ckpt, "ckpt"))) return rc;
+    if (nbody_checkpoint_bytes(n, steps, ckpt_every) == kInvalid)
+      return fail(NBODY_ERR_INVALID_ARGUMENT,
+                  "checkpoint buffer size overflows (n = %lld, steps = %lld)",
+                  (long long)n, (long long)steps);
   }
   if ((rc = check_ws(ws, ws_bytes, ws_step(n, precision)))) return rc;
 
@@ -528,9 +543,9 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
     return fail(NBODY_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x",
                 flags & ~NBODY_HALF_KICK_DRIFT);
   const bool kdk = !(flags & NBODY_HALF_KICK_DRIFT);
-  if (steps < 0)
-    return fail(NBODY_ERR_INVALID_ARGUMENT, "steps = %lld < 0",
-                (long long)steps);
+  if (!valid_steps(steps))
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "steps = %lld outside [0, %lld]",
+                (long long)steps, (long long)NBODY_MAX_STEPS);
   if (ckpt_every < 1)
     return fail(NBODY_ERR_INVALID_ARGUMENT, "ckpt_every = %lld < 1",
                 (long long)ckpt_every);
@@ -539,9 +554,12 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
       (rc = check_ptr(gmass, "gmass")))
     return rc;
   if (gacc_T && (rc = check_ptr(gacc_T, "gacc_T"))) return rc;
-  if ((rc = check_ws(ws, ws_bytes, ws_adjoint(n, steps, ckpt_every,
-                                              precision))))
-    return rc;
+  const size_t ws_need = ws_adjoint(n, steps, ckpt_every, precision);
+  if (ws_need == kInvalid || nbody_checkpoint_bytes(n, steps, ckpt_every) == kInvalid)
+    return fail(NBODY_ERR_INVALID_ARGUMENT,
+                "workspace or checkpoint size overflows (n = %lld, steps = %lld)",
+                (long long)n, (long long)steps);
+  if ((rc = check_ws(ws, ws_bytes, ws_need))) return rc;
 
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int nn = int(n);
@@ -718,9 +736,9 @@ int nbody_step_f32(int64_t n, int64_t steps, float *pos, float *vel,
                    unsigned flags, void *ws, size_t ws_bytes, void *stream) {
   int rc;
   if ((rc = check_f32(n, p, true))) return rc;
-  if (steps < 0)
-    return fail(NBODY_ERR_INVALID_ARGUMENT, "steps = %lld < 0",
-                (long long)steps);
+  if (!valid_steps(steps))
+    return fail(NBODY_ERR_INVALID_ARGUMENT, "steps = %lld outside [0, %lld]",
+                (long long)steps, (long long)NBODY_MAX_STEPS);
   if (flags & ~(NBODY_ACC_VALID | NBODY_HALF_KICK_DRIFT))
     return fail(NBODY_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x",
                 flags & ~(NBODY_ACC_VALID | NBODY_HALF_KICK_DRIFT));

@@ -362,3 +362,34 @@ def test_f32_rejects_invalid_arguments(B):
     assert step(vel=0) == 1
     assert step(dt=1e300) == 1
     assert step(wsb=ws - 4) == 2
+
+
+# ------------------------------------------------------ size overflow guards --
+
+def test_step_counts_and_sizes_cannot_overflow(B):
+    inv = ctypes.c_size_t(-1).value
+    big_n, max_steps = 1 << 28, 1 << 40
+    assert "#define NBODY_MAX_STEPS ((int64_t)1 << 40)" in open(HEADER).read()
+    # 2^40 records of 9 * 2^28 doubles is far beyond 2^62 bytes
+    assert B.nbody_checkpoint_bytes(big_n, max_steps, 1) == inv
+    assert B.nbody_checkpoint_bytes(100, max_steps + 1, 1) == inv
+    assert B.nbody_checkpoint_bytes(100, max_steps, max_steps) == 9 * 100 * 8
+    assert B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, big_n, max_steps,
+                                   max_steps, 0) == inv
+    assert B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, 100, max_steps + 1,
+                                   1, 0) == inv
+    lib = B.load_library()
+    # rejected on the host before anything is enqueued
+    rc = lib.nbody_step(100, max_steps + 1, _p(FAKE), _p(FAKE), _p(FAKE), _p(FAKE),
+                        _params(B), 0, 0, None, 0, _p(FAKE), 1 << 40, None)
+    assert rc == 1 and "steps" in lib.nbody_last_error().decode()
+    rc = lib.nbody_step(big_n, max_steps, _p(FAKE), _p(FAKE), _p(FAKE), _p(FAKE),
+                        _params(B), 0, 0, _p(FAKE), 1, _p(FAKE), 1 << 62, None)
+    assert rc == 1 and "overflows" in lib.nbody_last_error().decode()
+    rc = lib.nbody_step_adjoint(big_n, max_steps, max_steps, _p(FAKE), _p(FAKE),
+                                _params(B), 0, 0, _p(FAKE), _p(FAKE), None, _p(FAKE),
+                                _p(FAKE), 1 << 62, None)
+    assert rc == 1 and "overflows" in lib.nbody_last_error().decode()
+    rc = lib.nbody_step_f32(100, max_steps + 1, _p(FAKE), _p(FAKE), _p(FAKE), _p(FAKE),
+                            _params(B), 0, _p(FAKE), 1 << 40, None)
+    assert rc == 1
