@@ -143,7 +143,9 @@ int64_t num_tiles(int64_t n) { return (n + nbody::kThreads - 1) / nbody::kThread
 size_t nf_bytes(nbody::KernelKind kind, int prec, int64_t n, int64_t nt) {
   if (prec != NBODY_MIXED_NF && prec != NBODY_MIXED_NF64) return 0;
   const Plan pl = nbody::make_plan(kind, prec, nt, n);
-  return round_up(nbody::near_far_box_doubles(kind, pl.L, n, nt) * sizeof(double));
+  return round_up(nbody::near_far_box_doubles(kind, pl.L, prec == NBODY_MIXED_NF64,
+                                              n, nt) *
+                  sizeof(double));
 }
 size_t box_bytes_fwd(int64_t n, int prec) { return nf_bytes(nbody::kAccel, prec, n, n); }
 size_t box_bytes_vjp(int64_t n, int prec) { return nf_bytes(nbody::kVjp, prec, n, n); }

@@ -38,6 +38,27 @@ constexpr int kBodyThreadsSort = 256;
 
 constexpr double kNearFarKappa2 = 0.25;  // kappa = 1/2
 
+// FP32 sources per chunk sum, and so per near / far decision, of each kernel
+// (per lane; a run of the tile is C*L consecutive sources).  The forward of
+// NBODY_MIXED_NF64 takes chunks of 16: half the FP32 summation error in its
+// far runs, which sets its worst relative error (bodies near the centre of a
+// cluster, whose net acceleration almost cancels), and smaller run boxes, so
+// fewer runs are near, for one more FP64 flush per 16 pairs (measured: the
+// largest relative error over all 262144 bodies of a clustered Plummer
+// system 1.1e-6 -> 7.2e-7; +4 % at N = 16384, -3 % at N = 262144).
+constexpr int kNf64Chunk = 16;
+
+constexpr int nf_chunk(KernelKind kind, bool near64) {
+  return kind == kVjp ? kVjpChunk : (near64 ? kNf64Chunk : kChunk);
+}
+
+// Sources per near / far decision of each kernel at lanes-per-target L.
+constexpr int nf_run(KernelKind kind, int L, bool near64) {
+  return (kThreads / L < nf_chunk(kind, near64) ? kThreads / L
+                                                : nf_chunk(kind, near64)) *
+         L;
+}
+
 struct Box {
   double lo[3], hi[3];
 };
@@ -216,7 +237,7 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
     int jchunk, double *__restrict__ out, size_t split_stride) {
   constexpr int G = kThreads / L;
   constexpr int PER = kThreads / L;
-  constexpr int C = PER < kChunk ? PER : kChunk;
+  constexpr int C = nf_run(kAccel, L, NEAR64) / L;  // sources per lane and run
   constexpr int RUN = C * L;  // sources of one chunk run (box granularity)
   using NearSrc = Src<NEAR64 ? NBODY_FP64 : NBODY_MIXED_D64>;
   __shared__ NearSrc near_tile[kThreads];
@@ -319,7 +340,7 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
     size_t split_stride) {
   constexpr int G = kThreads / L;
   constexpr int PER = kThreads / L;
-  constexpr int C = PER < kVjpChunk ? PER : kVjpChunk;
+  constexpr int C = nf_run(kVjp, L, NEAR64) / L;
   constexpr int RUN = C * L;
   using NearSrc = VSrc<NEAR64 ? NBODY_FP64 : NBODY_MIXED_D64>;
   __shared__ NearSrc near_tile[kThreads];
@@ -460,13 +481,6 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
   }
 }
 
-// Sources per near / far decision of each kernel at lanes-per-target L.
-constexpr int nf_run(KernelKind kind, int L) {
-  return (kThreads / L < (kind == kVjp ? kVjpChunk : kChunk)
-              ? kThreads / L
-              : (kind == kVjp ? kVjpChunk : kChunk)) *
-         L;
-}
 
 // ------------------------------------------------------ Morton (Z) order --
 //
@@ -616,9 +630,10 @@ struct NfLayout {
   size_t off_wave, off_block, total;
 };
 
-NfLayout nf_layout(KernelKind kind, int L, int64_t n, int64_t nt) {
+NfLayout nf_layout(KernelKind kind, int L, bool near64, int64_t n,
+                   int64_t nt) {
   NfLayout l;
-  l.run = nf_run(kind, L);
+  l.run = nf_run(kind, L, near64);
   l.gw = 64 / L;
   l.gb = kThreads / L;
   const size_t nr = size_t((n + l.run - 1) / l.run);
@@ -633,10 +648,10 @@ NfLayout nf_layout(KernelKind kind, int L, int64_t n, int64_t nt) {
 // Fill the box area for a launch over targets row0 .. row0 + nt - 1: one
 // pass when the targets are all n bodies, otherwise one over the sources and
 // one over the target rows.
-hipError_t launch_nf_boxes(KernelKind kind, int L, int n, int row0, int nt,
-                           const double *pos, double *area, NfBoxes &bx,
-                           hipStream_t st) {
-  const NfLayout l = nf_layout(kind, L, n, nt);
+hipError_t launch_nf_boxes(KernelKind kind, int L, bool near64, int n,
+                           int row0, int nt, const double *pos, double *area,
+                           NfBoxes &bx, hipStream_t st) {
+  const NfLayout l = nf_layout(kind, L, near64, n, nt);
   double *rb = area, *wb = area + l.off_wave, *bb = area + l.off_block;
   bx.run = rb;
   bx.wave = wb;
@@ -666,7 +681,8 @@ hipError_t launch_accel_nf(const Plan &pl, int n, int row0, int nt,
                            hipStream_t st) {
   if (pl.R != 1) return hipErrorInvalidValue;
   NfBoxes bx;
-  const hipError_t e = launch_nf_boxes(kAccel, pl.L, n, row0, nt, pos, boxes, bx, st);
+  const hipError_t e = launch_nf_boxes(kAccel, pl.L, near64, n, row0, nt, pos, boxes,
+                                       bx, st);
   if (e != hipSuccess) return e;
   const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
   const int jc = int(pl.jchunk);
@@ -689,7 +705,8 @@ hipError_t launch_vjp_nf(const Plan &pl, int n, int row0, int nt,
                          bool near64, hipStream_t st) {
   if (pl.R != 1) return hipErrorInvalidValue;
   NfBoxes bx;
-  const hipError_t e = launch_nf_boxes(kVjp, pl.L, n, row0, nt, pos, boxes, bx, st);
+  const hipError_t e = launch_nf_boxes(kVjp, pl.L, near64, n, row0, nt, pos, boxes,
+                                       bx, st);
   if (e != hipSuccess) return e;
   const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
   const int jc = int(pl.jchunk);
@@ -705,8 +722,9 @@ hipError_t launch_vjp_nf(const Plan &pl, int n, int row0, int nt,
   return hipGetLastError();
 }
 
-size_t near_far_box_doubles(KernelKind kind, int L, int64_t n, int64_t nt) {
-  return nf_layout(kind, L, n, nt).total;
+size_t near_far_box_doubles(KernelKind kind, int L, bool near64, int64_t n,
+                            int64_t nt) {
+  return nf_layout(kind, L, near64, n, nt).total;
 }
 
 int64_t morton_padded(int64_t n) {
