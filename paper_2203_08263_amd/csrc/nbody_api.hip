@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <utility>
 
 #include "../../include/nbody.h"
 #include "nbody_internal.h"
@@ -155,9 +156,27 @@ size_t ws_accel(int64_t n, int prec) {
   const Plan pl = nbody::make_plan(nbody::kAccel, prec, n);
   return box_bytes_fwd(n, prec) + (pl.sj > 1 ? dbytes(pl.sj * 3 * n) : 0);
 }
+// Small systems are launch-bound: their step loop runs one launch per step
+// (the force with one wave per target over all sources, then the update of
+// that target), alternating positions between pos and a workspace copy.
+// With one wave per target such a launch holds n / 4 workgroups, too few
+// waves to hide latency as n grows; measured crossovers against the two-launch
+// loop (100 steps, HIP graph): FP64 wins up to n = 2048 (-40 % per step at
+// n <= 256, -15 % at 1024, -4 % at 2048); the FP32-pair modes, whose pairs
+// are cheaper, up to about n = 512 (-22 % at 256, +2 % at 1024).
+bool small_step(int prec, int64_t n) {
+  switch (prec) {
+    case NBODY_FP64: return n <= 2048;
+    case NBODY_MIXED_D64: return n <= 1024;
+    case NBODY_MIXED: return n <= 512;
+    default: return false;
+  }
+}
+
 size_t ws_step(int64_t n, int prec) {
   const Plan pl = nbody::make_plan(nbody::kAccel, prec, n);
-  return box_bytes_fwd(n, prec) + dbytes(pl.sj * 3 * n);
+  return box_bytes_fwd(n, prec) + dbytes(pl.sj * 3 * n) +
+         (small_step(prec, n) ? dbytes(3 * n) : 0);
 }
 size_t ws_vjp(int64_t n, int prec) {
   const Plan pl = nbody::make_plan(nbody::kVjp, prec, n);
@@ -464,17 +483,28 @@ int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
   const int nn = int(n);
   const double eps2 = p->eps * p->eps, G = p->G, dt = p->dt, h = 0.5 * dt;
   const Plan pl = nbody::make_plan(nbody::kAccel, precision, n);
-  double *boxes = ws_boxes(ws);
-  double *part = ws_parts(ws, box_bytes_fwd(n, precision));
   const size_t stride = size_t(3) * n;
   const size_t rec_len = size_t(9) * n;
+  // Workspace layout: boxes | split partials | (small systems) positions.
+  double *boxes = ws_boxes(ws);
+  double *part = ws_parts(ws, box_bytes_fwd(n, precision));
+  const bool small = small_step(precision, n);
+  double *xbuf = small ? reinterpret_cast<double *>(
+                             reinterpret_cast<char *>(part) +
+                             dbytes(pl.sj * 3 * n))
+                       : nullptr;
   hipError_t e;
 
   // Step 0: a_0 (computed or given), checkpoint record 0, opening half-kick
-  // and drift.  The paper's update has no closing half-kick.
+  // and drift.  The paper's update has no closing half-kick.  On the
+  // one-launch path every step reads the positions from one buffer and
+  // drifts them into the other; x_1 goes to the buffer that makes x_steps
+  // land in pos.
   const bool have_acc = flags & NBODY_ACC_VALID;
   const unsigned close_flag =
       (flags & NBODY_HALF_KICK_DRIFT) ? 0u : unsigned(nbody::kClose);
+  double *x_cur = (small && steps % 2 == 0) ? xbuf : pos;
+  double *x_next = x_cur == pos ? xbuf : pos;
   if (!have_acc) {
     if ((rc = accel_to_parts(pl, precision, nn, pos, mass, boxes, eps2, part,
                              st)))
@@ -482,20 +512,27 @@ int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
   }
   if (!have_acc || ckpt || steps > 0) {
     e = nbody::launch_update(nn, int(pl.sj), have_acc ? nullptr : part, stride,
-                             G, acc, have_acc ? nullptr : acc, pos, pos, vel,
-                             vel, h, dt, ckpt,
+                             G, acc, have_acc ? nullptr : acc, pos,
+                             steps > 0 ? x_cur : pos, vel, vel, h, dt, ckpt,
                              steps > 0 ? unsigned(nbody::kOpen) : 0u, st);
     if (e != hipSuccess) return hip_fail(e, "update kernel launch");
   }
   for (int64_t t = 0; t < steps; ++t) {
-    if ((rc = accel_to_parts(pl, precision, nn, pos, mass, boxes, eps2, part,
-                             st)))
-      return rc;
     const bool more = t + 1 < steps;
     double *rec = nullptr;
     if (ckpt && more && (t + 1) % ckpt_every == 0)
       rec = ckpt + size_t((t + 1) / ckpt_every) * rec_len;
     const unsigned fl = close_flag | (more ? unsigned(nbody::kOpen) : 0u);
+    if (small) {
+      e = nbody::launch_step_small(precision, nn, x_cur, mass, eps2, G, vel,
+                                   vel, x_next, acc, rec, h, dt, fl, st);
+      if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+      std::swap(x_cur, x_next);
+      continue;
+    }
+    if ((rc = accel_to_parts(pl, precision, nn, pos, mass, boxes, eps2, part,
+                             st)))
+      return rc;
     e = nbody::launch_update(nn, int(pl.sj), part, stride, G, nullptr, acc,
                              pos, pos, vel, vel, h, dt, rec, fl, st);
     if (e != hipSuccess) return hip_fail(e, "update kernel launch");
@@ -604,17 +641,23 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
                              nullptr, rec, seg, rec + 3 * n, v_ws, h, dt,
                              nullptr, nbody::kOpen, st);
     if (e != hipSuccess) return hip_fail(e, "update kernel launch");
+    const unsigned fl =
+        (kdk ? unsigned(nbody::kClose) : 0u) | unsigned(nbody::kOpen);
     for (int64_t t = 1; t < k; ++t) {
       const double *xp = seg + size_t(t - 1) * q3;
+      if (small_step(precision, n)) {
+        e = nbody::launch_step_small(precision, nn, xp, mass, eps2, G, v_ws,
+                                     v_ws, seg + size_t(t) * q3, a_ws, nullptr,
+                                     h, dt, fl, st);
+        if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+        continue;
+      }
       if ((rc = accel_to_parts(pf, precision, nn, xp, mass, boxes, eps2, part,
                                st)))
         return rc;
       e = nbody::launch_update(nn, int(pf.sj), part, q3, G, nullptr, a_ws, xp,
                                seg + size_t(t) * q3, v_ws, v_ws, h, dt,
-                               nullptr,
-                               (kdk ? unsigned(nbody::kClose) : 0u) |
-                                   unsigned(nbody::kOpen),
-                               st);
+                               nullptr, fl, st);
       if (e != hipSuccess) return hip_fail(e, "update kernel launch");
     }
     // Reverse sweep over steps s0+k-1 .. s0: VJP at x_{t+1} = seg[t - s0].

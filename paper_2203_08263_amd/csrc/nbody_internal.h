@@ -96,6 +96,16 @@ hipError_t launch_update(int n, int sj, const double *part, size_t stride,
                          double *v_out, double h, double dt, double *rec,
                          unsigned flags, hipStream_t st);
 
+// One time step of a small system in a single launch (NBODY_FP64,
+// NBODY_MIXED, NBODY_MIXED_D64): a = G * A(x_in) with one wave per target
+// and the whole source range in one sum, then update_kernel's per-entry
+// update with that a (x_in, x_out distinct buffers).
+hipError_t launch_step_small(int precision, int n, const double *x_in,
+                             const double *mass, double eps2, double G,
+                             const double *v_in, double *v_out, double *x_out,
+                             double *acc_out, double *rec, double h, double dt,
+                             unsigned flags, hipStream_t st);
+
 // Reverse sweep helpers (all FP64).
 //   abar = (gacc_T ? gacc_T : 0) + (add_hv ? h * gvel : 0);  gmass = 0
 hipError_t launch_adj_init(int n, const double *gvel, const double *gacc_T,

@@ -42,26 +42,24 @@ namespace {
 // of it when row0 = 0, nt = n), sources are all n bodies; output row i (of
 // stride nt) belongs to body row0 + i.
 
+// The sums of one lane: its share (tile entries q, q + L, ...) of the sources
+// jbeg .. jend - 1 acting on the R targets of its lane group, without G.
 template <int PREC, int R, int L>
-__global__ __launch_bounds__(kThreads) void accel_kernel(
+__device__ __forceinline__ void accel_lane_sums(
     int n, int row0, int nt, const double *__restrict__ pos,
-    const double *__restrict__ mass, double eps2d, double scale, int jchunk,
-    double *__restrict__ out, size_t split_stride) {
+    const double *__restrict__ mass, double eps2d, int jbeg, int jend,
+    Src<PREC> *tile, double (&ax)[R], double (&ay)[R], double (&az)[R]) {
   using CT = typename Coord<PREC>::T;
   using DT = typename Coord<PREC>::D;
   constexpr int G = kThreads / L;             // target groups per workgroup
   constexpr int PER = kThreads / L;           // tile entries per lane
   constexpr int C = PER < kChunk ? PER : kChunk;
-  __shared__ Src<PREC> tile[kThreads];
 
   const int tid = threadIdx.x;
   const int g = tid / L, q = tid % L;
   const int ibase = blockIdx.x * (G * R) + g;
-  const int jbeg = blockIdx.y * jchunk;
-  const int jend = min(n, jbeg + jchunk);
 
   CT xi[R], yi[R], zi[R];
-  double ax[R], ay[R], az[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = ibase + r * G;
@@ -112,6 +110,22 @@ __global__ __launch_bounds__(kThreads) void accel_kernel(
       }
     }
   }
+}
+
+template <int PREC, int R, int L>
+__global__ __launch_bounds__(kThreads) void accel_kernel(
+    int n, int row0, int nt, const double *__restrict__ pos,
+    const double *__restrict__ mass, double eps2d, double scale, int jchunk,
+    double *__restrict__ out, size_t split_stride) {
+  constexpr int G = kThreads / L;
+  __shared__ Src<PREC> tile[kThreads];
+  const int g = threadIdx.x / L, q = threadIdx.x % L;
+  const int ibase = blockIdx.x * (G * R) + g;
+  const int jbeg = blockIdx.y * jchunk;
+  const int jend = min(n, jbeg + jchunk);
+  double ax[R], ay[R], az[R];
+  accel_lane_sums<PREC, R, L>(n, row0, nt, pos, mass, eps2d, jbeg, jend, tile,
+                              ax, ay, az);
 
   double *o = out + size_t(blockIdx.y) * split_stride;
 #pragma unroll
@@ -351,14 +365,13 @@ __global__ __launch_bounds__(kBodyThreads) void reduce_kernel(
   else out_m[q - size_t(3) * n] = v;
 }
 
-__global__ __launch_bounds__(kBodyThreads) void update_kernel(
-    int n, int sj, const double *__restrict__ part, size_t stride, double G,
-    const double *a_in, double *acc_out, const double *x_in, double *x_out,
-    const double *v_in, double *v_out, double h, double dt, double *rec,
-    unsigned flags) {
-  const size_t q = size_t(blockIdx.x) * kBodyThreads + threadIdx.x;
-  if (q >= size_t(3) * n) return;
-  const double a = part ? G * split_sum(part, stride, sj, q) : a_in[q];
+// The state update of one (component, body) entry q of [3][n] with its new
+// acceleration a: closing half-kick, checkpoint record, opening half-kick and
+// drift (flags kClose / kOpen).
+__device__ __forceinline__ void update_entry(
+    int n, size_t q, double a, const double *x_in, double *x_out,
+    const double *v_in, double *v_out, double *acc_out, double h, double dt,
+    double *rec, unsigned flags) {
   const double x = x_in[q];
   double v = v_in[q];
   if (flags & kClose) v = v + h * a;
@@ -373,6 +386,44 @@ __global__ __launch_bounds__(kBodyThreads) void update_kernel(
   }
   v_out[q] = v;
   if (acc_out) acc_out[q] = a;
+}
+
+__global__ __launch_bounds__(kBodyThreads) void update_kernel(
+    int n, int sj, const double *__restrict__ part, size_t stride, double G,
+    const double *a_in, double *acc_out, const double *x_in, double *x_out,
+    const double *v_in, double *v_out, double h, double dt, double *rec,
+    unsigned flags) {
+  const size_t q = size_t(blockIdx.x) * kBodyThreads + threadIdx.x;
+  if (q >= size_t(3) * n) return;
+  const double a = part ? G * split_sum(part, stride, sj, q) : a_in[q];
+  update_entry(n, q, a, x_in, x_out, v_in, v_out, acc_out, h, dt, rec, flags);
+}
+
+// One whole time step of a small system in one launch: a wave per target
+// body (L = 64 lanes share it, kThreads / 64 targets per workgroup) sums the
+// force of all n sources, then its first lane applies update_entry to the
+// three components.  x_in must not alias x_out: every workgroup still reads
+// all of x_in while others write their drifted positions.
+template <int PREC>
+__global__ __launch_bounds__(kThreads) void step_small_kernel(
+    int n, const double *__restrict__ x_in, const double *__restrict__ mass,
+    double eps2d, double G, const double *v_in, double *v_out,
+    double *__restrict__ x_out, double *acc_out, double *rec, double h,
+    double dt, unsigned flags) {
+  constexpr int L = 64;
+  __shared__ Src<PREC> tile[kThreads];
+  double ax[1], ay[1], az[1];
+  accel_lane_sums<PREC, 1, L>(n, 0, n, x_in, mass, eps2d, 0, n, tile, ax, ay,
+                              az);
+  const double s[3] = {group_sum<L>(ax[0]), group_sum<L>(ay[0]),
+                       group_sum<L>(az[0])};
+  const int i = blockIdx.x * (kThreads / L) + int(threadIdx.x) / L;
+  if (threadIdx.x % L == 0 && i < n) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      update_entry(n, size_t(c) * n + i, G * s[c], x_in, x_out, v_in, v_out,
+                   acc_out, h, dt, rec, flags);
+  }
 }
 
 __global__ __launch_bounds__(kBodyThreads) void adj_init_kernel(
@@ -641,6 +692,25 @@ hipError_t launch_update(int n, int sj, const double *part, size_t stride,
   update_kernel<<<grid_body(n, 3), kBodyThreads, 0, st>>>(
       n, sj, part, stride, G, a_in, acc_out, x_in, x_out, v_in, v_out, h, dt,
       rec, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_small(int precision, int n, const double *x_in,
+                             const double *mass, double eps2, double G,
+                             const double *v_in, double *v_out, double *x_out,
+                             double *acc_out, double *rec, double h, double dt,
+                             unsigned flags, hipStream_t st) {
+  const dim3 grid(unsigned((n + kThreads / 64 - 1) / (kThreads / 64)));
+#define NBODY_STEP_SMALL(PREC_)                                              \
+  step_small_kernel<PREC_><<<grid, kThreads, 0, st>>>(                      \
+      n, x_in, mass, eps2, G, v_in, v_out, x_out, acc_out, rec, h, dt, flags)
+  switch (precision) {
+    case NBODY_FP64: NBODY_STEP_SMALL(NBODY_FP64); break;
+    case NBODY_MIXED: NBODY_STEP_SMALL(NBODY_MIXED); break;
+    case NBODY_MIXED_D64: NBODY_STEP_SMALL(NBODY_MIXED_D64); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef NBODY_STEP_SMALL
   return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import _tol
-from paper_2203_08263_amd import inputs
+from paper_2203_08263_amd import inputs, metrics
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -167,6 +167,39 @@ def test_step_parity_small(B, dev, oracle, prec):
         assert np.abs(N(P) - x).max() <= 2 * S * S * dt * dt * ab
     _check_bound(N(A), oracle.accel(N(P), mass, 1.0, eps),
                  _tol.accel_bound(N(P), mass, 1.0, eps, prec), "final acc")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_d64", "mixed"])
+@pytest.mark.parametrize("n,S", [(100, 1), (100, 2), (100, 3), (512, 4),
+                                 (513, 4), (1024, 3), (1025, 3), (2048, 2),
+                                 (2049, 2)])
+def test_step_one_launch_loop_sizes(B, dev, oracle, prec, n, S):
+    # small systems step in one launch per step (positions alternate between
+    # pos and a workspace copy; FP64 up to n = 2048, D64 up to 1024, mixed up
+    # to 512), larger ones in two: odd and even step counts on both sides of
+    # each limit, checked against the oracle with a checkpoint record
+    say("step sizes", prec, n, S)
+    pos, vel, mass, P, V, M = _state(n, 60 + n + S, dev)
+    A = torch.empty_like(P)
+    ck = torch.empty(B.nbody_checkpoint_bytes(n, S, 1) // 8, dtype=torch.float64,
+                     device=dev)
+    B.nbody_step(P, V, A, M, 1.0, 1e-3, 1e-3, S, prec, ckpt=ck, ckpt_every=1)
+    x, v, a = oracle.step(pos, vel, mass, 1.0, 1e-3, 1e-3, S)
+    if prec == "fp64":
+        assert metrics.normwise(N(P), x) <= 1e-12
+        assert metrics.normwise(N(V), v) <= 1e-12
+    else:
+        ab = _tol.accel_bound(pos, mass, 1.0, 1e-3, prec).max()
+        assert np.abs(N(V) - v).max() <= 2 * S * 1e-3 * ab
+        assert np.abs(N(P) - x).max() <= 2 * S * S * 1e-6 * ab
+    _check_bound(N(A), oracle.accel(N(P), mass, 1.0, 1e-3),
+                 _tol.accel_bound(N(P), mass, 1.0, 1e-3, prec), "final acc")
+    # the last record holds the state before the last step
+    xs, vs, as_ = oracle.step(pos, vel, mass, 1.0, 1e-3, 1e-3, S - 1)
+    rec = N(ck).reshape(-1, 9, n)[S - 1]
+    if prec == "fp64":
+        assert metrics.normwise(rec[0:3], xs) <= 1e-12
+        assert metrics.normwise(rec[6:9], as_) <= 1e-12
 
 
 @pytest.mark.parametrize("prec", PRECS)
