@@ -397,9 +397,10 @@ def adjoint_leg(torch, B, inputs):
 
 
 def small_rollout_leg(torch, B, inputs):
-    """The launch-bound configuration: N = 1024, 100 FP64 KDK steps (two
-    launches per step).  Timed eagerly and as a replayed HIP graph of the same
-    nbody_step call (state restored by device copies before each run)."""
+    """The launch-bound configuration: N = 1024, 100 FP64 KDK steps (one
+    launch per step at this size).  Timed eagerly and as a replayed HIP graph
+    of the same nbody_step call (state restored by device copies before each
+    run)."""
     dev = torch.device("cuda:0")
     w = inputs.WORKLOADS["cube1024_fp64"]
     T = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa
