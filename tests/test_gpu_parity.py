@@ -504,6 +504,38 @@ def test_translation_invariance(B, dev, prec):
     assert np.array_equal(a0, a1)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_system_far_from_origin(B, dev, oracle, prec):
+    # the same cube moved to (1000, -2000, 500): rounding absolute positions
+    # to FP32 (NBODY_MIXED) now costs u32 * 2000 per coordinate, which the
+    # bound carries; the FP64-difference and near / far modes round only
+    # differences (or box-relative coordinates) and keep their accuracy
+    say("far from origin", prec)
+    n = 3001
+    pos, _, mass = inputs.uniform_cube(n, 78)
+    pos = pos + np.array([[1000.0], [-2000.0], [500.0]])
+    if prec in ("mixed_nf", "mixed_nf64"):
+        o = oracle.morton_order(pos)
+        pos, mass = pos[:, o].copy(), mass[o].copy()
+    g = inputs.upstream_normal(n, 79)
+    a = N(B.nbody_accel(T(pos, dev), T(mass, dev), 1.0, 1e-3, prec))
+    ref = oracle.accel(pos, mass, 1.0, 1e-3)
+    err = _check_bound(a, ref, _tol.accel_bound(pos, mass, 1.0, 1e-3, prec), prec)
+    rel = float((err / np.linalg.norm(ref, axis=0)).max())
+    say("  E_max %.2e" % rel)
+    # measured: FP64 7e-15, D64 8e-7, NF 4e-7, NF64 1e-7 -- no loss to the
+    # offset -- against 1e-2 for plain mixed
+    if prec == "fp64":
+        assert rel <= 1e-12
+    elif prec != "mixed":
+        assert rel <= 1e-5
+    gx, gm = B.nbody_accel_vjp(T(pos, dev), T(mass, dev), T(g, dev), 1.0, 1e-3, prec)
+    rx, rm = oracle.accel_vjp(pos, mass, g, 1.0, 1e-3)
+    bx, bm = _tol.vjp_bound(pos, mass, g, 1.0, 1e-3, prec)
+    _check_bound(N(gx), rx, bx, prec + " dL/dx")
+    assert np.all(np.abs(N(gm) - rm) <= bm), prec + " dL/dm"
+
+
 def test_vjp_dot_product_test_fp64(B, dev):
     # <gbar, J dx> by central differences of the GPU forward equals
     # <J^T gbar, dx> from the GPU VJP (both FP64).
