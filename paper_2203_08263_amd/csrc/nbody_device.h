@@ -20,16 +20,19 @@ constexpr int kBodyThreads = 64;  // threads per workgroup, per-body kernels
 
 // -------------------------------------------------------------- arithmetic --
 
-// 1/sqrt(s) in FP64: hardware estimate (about 23 correct bits) refined by two
-// Newton steps y <- y (3 - s y^2) / 2, written as y + y (1/2 - (s/2) y y).
+// 1/sqrt(s) in FP64: the hardware estimate y0 refined by one third-order
+// step.  With e = 1 - s y0^2, s^(-1/2) = y0 (1 - e)^(-1/2) = y0 (1 + e/2 +
+// 3e^2/8 + O(e^3)), so y0 + (y0 e)(1/2 + 3e/8) leaves a truncation error of
+// about 2.5 d^3 for an estimate of relative error d.  The estimate is within
+// 2^-24 of s^(-1/2) (measured over 4M arguments spanning 2^-60 .. 2^60), so
+// that is far below one rounding; emulated with exact FMAs the step is within
+// 1.23 units of 2^-53 for any |d| <= 2^-21, as two Newton steps are.  Five
+// FP64 operations instead of the seven of two Newton steps.
 __device__ __forceinline__ double rsqrt_f64(double s) {
-  double y = __builtin_amdgcn_rsq(s);
-  const double hs = 0.5 * s;
-  double e = fma(-(hs * y), y, 0.5);
-  y = fma(y, e, y);
-  e = fma(-(hs * y), y, 0.5);
-  y = fma(y, e, y);
-  return y;
+  const double y = __builtin_amdgcn_rsq(s);
+  const double e = fma(-(s * y), y, 1.0);
+  const double p = fma(e, 0.375, 0.5);
+  return fma(y * e, p, y);
 }
 
 __device__ __forceinline__ float rsqrt_f32(float s) {

@@ -22,7 +22,7 @@
 // direct-summation force of arxiv 2203.08263 section 2.3 (force loop of the
 // section 3.2 / 3.3 listings) with the acceleration taken directly as
 // G sum_j m_j d s^-3/2 and the reciprocal square root from the hardware
-// approximation (v_rsq_f32 / v_rsq_f64), refined by Newton's method in FP64.
+// approximation (v_rsq_f32 / v_rsq_f64), refined in FP64 by one third-order step.
 #include <algorithm>
 
 #include "nbody_device.h"
