@@ -8,8 +8,13 @@
 // iterations and writes one value, so the loop cannot be removed; the grid
 // covers every compute unit many times over.  Rates are reported per second
 // of wall time measured with HIP events on one stream, in lane-operations
-// (one lane executing one instruction).  Output: one JSON object per line.
+// (one lane executing one instruction).  It also measures the accuracy of
+// the two hardware reciprocal square root estimates (largest relative error
+// over 4M arguments spread over many binades), which sets how much
+// refinement the FP64 kernels need.  Output: one JSON object per line.
 #include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -91,6 +96,32 @@ __global__ __launch_bounds__(kThreads) void cvt_chain(int iters, double seed,
   out[blockIdx.x * kThreads + threadIdx.x] = s;
 }
 
+// Relative error |1 - s y^2| / 2 of the hardware estimate y of s^(-1/2):
+// FP64 arguments in [2^-60, 2^60), FP32 ones in [2^-20, 2^20), mantissas
+// from a counter-based hash of the sample index.
+__device__ double hash_u01(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdULL;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ULL;
+  k ^= k >> 33;
+  return double(k >> 11) * (1.0 / 9007199254740992.0);
+}
+
+__global__ __launch_bounds__(kThreads) void rsq_accuracy(int n, double *err64,
+                                                         double *err32) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const double m = 1.0 + hash_u01(2 * uint64_t(i));
+  const int ex = int(hash_u01(2 * uint64_t(i) + 1) * 120.0) - 60;
+  const double s = ldexp(m, ex);
+  const double y = __builtin_amdgcn_rsq(s);
+  err64[i] = fabs(fma(-(s * y), y, 1.0)) * 0.5;
+  const float sf = float(ldexp(m, ex / 3));
+  const float yf = __builtin_amdgcn_rsqf(sf);
+  err32[i] = fabs(1.0 - double(sf) * double(yf) * double(yf)) * 0.5;
+}
+
 template <typename K>
 static double time_ms(K launch, hipStream_t st) {
   hipEvent_t e0, e1;
@@ -149,6 +180,24 @@ int main(int argc, char **argv) {
          time_ms([&] { fma12_rsq1<<<blocks, kThreads, 0, st>>>(iters, 1.0f, f); }, st), 13);
   report("cvt_f32_f64+cvt_f64_f32+mul_f64 (per op)",
          time_ms([&] { cvt_chain<<<blocks, kThreads, 0, st>>>(iters, 1.0, d); }, st), 3);
+
+  const int nacc = 1 << 22;
+  double *err = nullptr;
+  CHECK(hipMalloc(&err, size_t(2) * nacc * sizeof(double)));
+  rsq_accuracy<<<nacc / kThreads, kThreads, 0, st>>>(nacc, err, err + nacc);
+  CHECK(hipGetLastError());
+  CHECK(hipStreamSynchronize(st));
+  double *h = static_cast<double *>(malloc(size_t(2) * nacc * sizeof(double)));
+  if (!h) return 1;
+  CHECK(hipMemcpy(h, err, size_t(2) * nacc * sizeof(double), hipMemcpyDeviceToHost));
+  for (int k = 0; k < 2; ++k) {
+    double w = 0.0;
+    for (int i = 0; i < nacc; ++i) w = fmax(w, h[size_t(k) * nacc + i]);
+    printf("{\"op\": \"%s accuracy\", \"samples\": %d, \"max_rel_err\": %.4e, "
+           "\"log2\": %.2f}\n", k ? "v_rsq_f32" : "v_rsq_f64", nacc, w, log2(w));
+  }
+  free(h);
+  CHECK(hipFree(err));
   CHECK(hipStreamDestroy(st));
   CHECK(hipFree(buf));
   return 0;
