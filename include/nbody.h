@@ -84,7 +84,9 @@ typedef struct nbody_params {
  *  NBODY_MIXED_NF64 as NBODY_MIXED_NF, but near runs use the FP64 pair and add
  *                   it straight into the FP64 sums, so close pairs -- whose
  *                   FP32 rounding dominates the mixed modes' error when
- *                   forces nearly cancel -- carry FP64 error only.  In a
+ *                   forces nearly cancel -- carry FP64 error only; the
+ *                   forward's runs and FP32 chunk sums span 16 sources per
+ *                   lane instead of 32.  In a
  *                   random order every run is near and the arithmetic is
  *                   FP64 throughout.  nbody_diagnostics evaluates W in FP64. */
 enum nbody_precision {
