@@ -16,10 +16,13 @@ One benchmark step is one pass of the whole hot path over that input:
 pairs included, 20 flops per pair).  Inputs are resident in HBM before the
 timed region; every step restores the initial state with device copies.
 
-Also reported on the same line: forward-only and FP64 / mixed-D64 legs, the
-roofline position of the dominant kernel (timed with HIP events on the
-stream it runs on), the stated errors against the FP64 oracle, and the
-oracle itself timed on the host cores (cpu_baseline).
+Also reported on the same line: forward-only and forward + adjoint legs of
+every precision (the near / far ones on the bodies in Morton order), the
+checkpoint-interval sweep and the FP32-state forward; kernel-level rates at
+N = 65536 and 262144 (whole system and one eighth of the target rows); the
+roofline position of the dominant kernel and of the forward (timed with HIP
+events on the stream they run on); the stated errors against the FP64
+oracle; and the oracle itself timed on the host cores (cpu_baseline).
 """
 from __future__ import annotations
 
