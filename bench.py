@@ -503,6 +503,55 @@ def cpu_baseline(bench, p, gx_gpu, gv_gpu, gm_gpu, x_end, v_end, finals=None):
     return base, err
 
 
+def cpu_by_workload(inputs):
+    """The FP64 oracle's rate on a bounded sample of each other workload
+    (about 3 s in all), for the per-workload GPU legs beside it."""
+    import numpy as np
+
+    import oracle
+
+    out = {}
+
+    def rate(pairs, fn):
+        t0 = time.perf_counter()
+        fn()
+        dt = time.perf_counter() - t0
+        return round(pairs / dt / 1e9, 3), round(dt, 3)
+
+    w = inputs.WORKLOADS["cube1024_fp64"]
+    pos, vel, mass = w.initial_state()
+    out["cube1024_fp64"] = dict(zip(("G_int_s", "s"), rate(
+        float(w.n) ** 2 * w.steps,
+        lambda: oracle.step(pos, vel, mass, w.G, w.eps, w.dt, w.steps))),
+        sample="the whole 100-step rollout")
+    w = inputs.WORKLOADS["plummer65536"]
+    pos, vel, mass = w.initial_state()
+    rows = w.rows(4096)
+    out["plummer65536"] = dict(zip(("G_int_s", "s"), rate(
+        float(len(rows)) * w.n,
+        lambda: oracle.accel_rows(pos, mass, w.G, w.eps, rows))),
+        sample="forces on the 4096 seeded rows")
+    w = inputs.WORKLOADS["cube8192_adjoint"]
+    pos, vel, mass = w.initial_state()
+    out["cube8192_adjoint"] = dict(zip(("G_int_s", "s"), rate(
+        float(w.n) ** 2 * w.steps,
+        lambda: oracle.step(pos, vel, mass, w.G, w.eps, w.dt, w.steps))),
+        sample="the 50-step forward rollout")
+    w = inputs.WORKLOADS["plummer262144_vjp"]
+    pos, _, mass = w.initial_state()
+    rows = w.rows(1024)
+    g = inputs.upstream_normal(w.n, w.seed + 400)
+
+    def both():
+        oracle.accel_rows(pos, mass, w.G, w.eps, rows)
+        oracle.accel_vjp_rows(pos, mass, g, w.G, w.eps, rows)
+    out["plummer262144_vjp"] = dict(zip(("G_int_s", "s"), rate(
+        2.0 * len(rows) * w.n, both)),
+        sample="force and VJP rows of the 1024 seeded bodies")
+    _ = np
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -642,6 +691,9 @@ def main(argv=None):
         base, err = cpu_baseline(bench, p, gx, gv, gm, x_end, v_end, finals)
         out["cpu_baseline"] = base
         out["error"] = err
+        if not args.no_shapes:
+            out["cpu_oracle_by_workload"] = cpu_by_workload(inputs)
+            log("bench: oracle by workload %s" % out["cpu_oracle_by_workload"])
     else:
         out["cpu_baseline"] = None
     _ = np
