@@ -80,6 +80,37 @@ def test_accel_golden_two_body(B, dev, prec):
     np.testing.assert_allclose(got, exact, rtol=tol, atol=0)
 
 
+def test_fp64_pair_within_ulps_across_scales(B, dev):
+    # the FP64 pair (hardware reciprocal square root refined in FP64) against
+    # the exact value of G m2 d (|d|^2 + eps^2)^(-3/2), computed with 60-digit
+    # decimals, for two bodies over 24 decades of separation and softening:
+    # 3 FMAs for s, the refined 1/sqrt (about 1.2 ulp), two products for
+    # m y^3 and the final product leave at most a few ulp
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    say("fp64 pair ulps")
+    rng = np.random.default_rng(2024)
+    worst = 0.0
+    for k in range(160):
+        scale = 10.0 ** rng.uniform(-12, 12)
+        d = rng.normal(size=3) * scale
+        eps = scale * 10.0 ** rng.uniform(-3, 1)
+        m2 = 10.0 ** rng.uniform(-3, 3)
+        pos = np.array([[0.0, d[0]], [0.0, d[1]], [0.0, d[2]]])
+        mass = np.array([1.0, m2])
+        a = N(B.nbody_accel(T(pos, dev), T(mass, dev), 1.0, eps, "fp64"))[:, 0]
+        D = [Decimal(float(x)) for x in d]
+        S = sum(x * x for x in D) + Decimal(float(eps)) * Decimal(float(eps))
+        w = Decimal(float(m2)) / (S * S.sqrt())
+        for c in range(3):
+            exact = w * D[c]
+            ulp = np.spacing(abs(float(exact)))
+            err = abs(Decimal(float(a[c])) - exact) / Decimal(float(ulp))
+            worst = max(worst, float(err))
+    say("  worst %.2f ulp" % worst)
+    assert worst <= 8.0
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_accel_edge_cases(B, dev, oracle, prec):
     say("edge cases", prec)
