@@ -283,14 +283,17 @@ def test_plummer262144_accel_vjp(B, dev, oracle, prec):
 
 # ------------------------------- largest size in the suite: N = 2^20 + 5 --
 
-@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("prec", ["mixed", "fp64", "mixed_d64", "mixed_nf64"])
 def test_large_ragged_system_sampled_rows(B, dev, oracle, prec):
     # 1048581 bodies (a ragged last tile; 1.1e12 pairs per call): accel and
     # VJP on 128 seeded rows against the oracle's rows, every row of the
-    # output finite
+    # output finite (the near / far mode on the bodies in Morton order)
     n = (1 << 20) + 5
     say("large", n, prec)
     pos, _, mass = inputs.uniform_cube(n, 3001)
+    if prec == "mixed_nf64":
+        o = oracle.morton_order(pos)
+        pos, mass = pos[:, o].copy(), mass[o].copy()
     g = inputs.upstream_normal(n, 3002)
     rows = inputs.subset_rows(n, 128, 3003)
     rows[-1] = n - 1                      # include the very last body
