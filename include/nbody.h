@@ -80,6 +80,8 @@ typedef struct nbody_params {
  *                   speed when the bodies are in a spatial order
  *                   (nbody_morton_sort); in a random order every run is near
  *                   and results are bitwise those of NBODY_MIXED_D64.
+ *                   A system of at most 1024 bodies counts every run as
+ *                   near: it is evaluated exactly as NBODY_MIXED_D64.
  *                   nbody_diagnostics evaluates W as NBODY_MIXED_D64.
  *  NBODY_MIXED_NF64 as NBODY_MIXED_NF, but near runs use the FP64 pair and add
  *                   it straight into the FP64 sums, so close pairs -- whose
@@ -88,7 +90,13 @@ typedef struct nbody_params {
  *                   forward's runs and FP32 chunk sums span 16 sources per
  *                   lane instead of 32.  In a
  *                   random order every run is near and the arithmetic is
- *                   FP64 throughout.  nbody_diagnostics evaluates W in FP64. */
+ *                   FP64 throughout; a system of at most 2048 bodies is
+ *                   evaluated exactly as NBODY_FP64.  nbody_diagnostics
+ *                   evaluates W in FP64.
+ * Every force evaluation of a small system (NBODY_FP64 up to 2048 bodies,
+ * NBODY_MIXED_D64 up to 1024, NBODY_MIXED up to 512) sums in one order,
+ * whether it comes from nbody_accel, the row-range form or nbody_step, whose
+ * loop then takes one launch per step. */
 enum nbody_precision {
   NBODY_FP64 = 0,
   NBODY_MIXED = 1,

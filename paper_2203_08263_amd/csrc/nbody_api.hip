@@ -20,11 +20,55 @@ namespace nbody {
 
 // ------------------------------------------------------------ launch plans --
 
+// Small systems are launch-bound: their step loop runs one launch per step
+// (the force with one wave per target over all sources, then the update of
+// that target), alternating positions between pos and a workspace copy.
+// With one wave per target such a launch holds n / 4 workgroups, too few
+// waves to hide latency as n grows; measured crossovers against the two-launch
+// loop (100 steps, HIP graph): FP64 wins up to n = 2048 (-40 % per step at
+// n <= 256, -15 % at 1024, -4 % at 2048); the FP32-pair modes, whose pairs
+// are cheaper, up to about n = 512 (-22 % at 256, +2 % at 1024).  Every
+// force evaluation of such a system -- nbody_accel, the row-range form, the
+// step's first one -- uses the same shape (one wave per target, no source
+// split), so all of them sum in one order: A(x) is one function, and a
+// rollout run backwards retraces its steps.
+bool small_system(int precision, int64_t n) {
+  switch (precision) {
+    case NBODY_FP64: return n <= 2048;
+    case NBODY_MIXED_D64: return n <= 1024;
+    case NBODY_MIXED: return n <= 512;
+    default: return false;
+  }
+}
+
+// The arithmetic a near / far precision stands for in a system of n bodies:
+// a small system counts every run as near -- in a launch-bound system the
+// split saves nothing and its box pass would add a launch -- which is
+// exactly NBODY_MIXED_D64 for NBODY_MIXED_NF and NBODY_FP64 for
+// NBODY_MIXED_NF64 (with their small-system shapes and one-launch steps).
+int effective_precision(int precision, int64_t n) {
+  if (precision == NBODY_MIXED_NF && small_system(NBODY_MIXED_D64, n))
+    return NBODY_MIXED_D64;
+  if (precision == NBODY_MIXED_NF64 && small_system(NBODY_FP64, n))
+    return NBODY_FP64;
+  return precision;
+}
+
 Plan make_plan(KernelKind kind, int precision, int64_t n) {
   return make_plan(kind, precision, n, n);
 }
 
 Plan make_plan(KernelKind kind, int precision, int64_t nt, int64_t n) {
+  if (kind == kAccel && small_system(precision, n)) {
+    // one wave per target, every source in one sum (the small-system step)
+    const int64_t ntiles = (n + kThreads - 1) / kThreads;
+    return Plan{1, 64, (nt + kThreads / 64 - 1) / (kThreads / 64), 1,
+                ntiles * kThreads};
+  }
+  return make_plan_general(kind, precision, nt, n);
+}
+
+Plan make_plan_general(KernelKind kind, int precision, int64_t nt, int64_t n) {
   // Chosen from launch-shape sweeps on MI355X (all-pairs kernel plus split
   // reduction).  Targets per lane R: 2 for FP64, 1 for the FP32-pair modes
   // (their pair chain is latency-bound, so more resident waves beat more
@@ -156,27 +200,10 @@ size_t ws_accel(int64_t n, int prec) {
   const Plan pl = nbody::make_plan(nbody::kAccel, prec, n);
   return box_bytes_fwd(n, prec) + (pl.sj > 1 ? dbytes(pl.sj * 3 * n) : 0);
 }
-// Small systems are launch-bound: their step loop runs one launch per step
-// (the force with one wave per target over all sources, then the update of
-// that target), alternating positions between pos and a workspace copy.
-// With one wave per target such a launch holds n / 4 workgroups, too few
-// waves to hide latency as n grows; measured crossovers against the two-launch
-// loop (100 steps, HIP graph): FP64 wins up to n = 2048 (-40 % per step at
-// n <= 256, -15 % at 1024, -4 % at 2048); the FP32-pair modes, whose pairs
-// are cheaper, up to about n = 512 (-22 % at 256, +2 % at 1024).
-bool small_step(int prec, int64_t n) {
-  switch (prec) {
-    case NBODY_FP64: return n <= 2048;
-    case NBODY_MIXED_D64: return n <= 1024;
-    case NBODY_MIXED: return n <= 512;
-    default: return false;
-  }
-}
-
 size_t ws_step(int64_t n, int prec) {
   const Plan pl = nbody::make_plan(nbody::kAccel, prec, n);
   return box_bytes_fwd(n, prec) + dbytes(pl.sj * 3 * n) +
-         (small_step(prec, n) ? dbytes(3 * n) : 0);
+         (nbody::small_system(prec, n) ? dbytes(3 * n) : 0);
 }
 size_t ws_vjp(int64_t n, int prec) {
   const Plan pl = nbody::make_plan(nbody::kVjp, prec, n);
@@ -232,7 +259,11 @@ int check_rows(int64_t n, int64_t row_begin, int64_t row_count) {
 // ---- FP32 state
 size_t fbytes(int64_t count) { return round_up(size_t(count) * sizeof(float)); }
 
-Plan plan_f32(int64_t n) { return nbody::make_plan(nbody::kAccel, NBODY_MIXED, n); }
+// The FP32-state kernels take the mixed mode's general plan shapes (they have
+// no small-system step).
+Plan plan_f32(int64_t n) {
+  return nbody::make_plan_general(nbody::kAccel, NBODY_MIXED, n, n);
+}
 
 size_t ws_accel_f32(int64_t n) {
   const Plan pl = plan_f32(n);
@@ -321,6 +352,7 @@ const char *nbody_last_error(void) { return g_last_error; }
 size_t nbody_workspace_bytes(int op, int64_t n, int64_t steps,
                              int64_t ckpt_every, int precision) {
   if (n < 1 || n > NBODY_MAX_N || !valid_precision(precision)) return kInvalid;
+  precision = nbody::effective_precision(precision, n);
   switch (op) {
     case NBODY_OP_ACCEL: return ws_accel(n, precision);
     case NBODY_OP_STEP: return ws_step(n, precision);
@@ -339,6 +371,7 @@ size_t nbody_rows_workspace_bytes(int op, int64_t n, int64_t row_count,
   if (n < 1 || n > NBODY_MAX_N || !valid_precision(precision) ||
       row_count < 0 || row_count > n)
     return kInvalid;
+  precision = nbody::effective_precision(precision, n);
   switch (op) {
     case NBODY_OP_ACCEL: return ws_accel_rows(n, row_count, precision);
     case NBODY_OP_VJP: return ws_vjp_rows(n, row_count, precision);
@@ -357,6 +390,7 @@ int nbody_accel(int64_t n, const double *pos, const double *mass, double *acc,
                 size_t ws_bytes, void *stream) {
   int rc;
   if ((rc = check_common(n, p, precision, false))) return rc;
+  precision = nbody::effective_precision(precision, n);
   if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(mass, "mass")) ||
       (rc = check_ptr(acc, "acc")))
     return rc;
@@ -388,6 +422,7 @@ int nbody_accel_rows(int64_t n, int64_t row_begin, int64_t row_count,
                      size_t ws_bytes, void *stream) {
   int rc;
   if ((rc = check_common(n, p, precision, false))) return rc;
+  precision = nbody::effective_precision(precision, n);
   if ((rc = check_rows(n, row_begin, row_count))) return rc;
   if (row_count == 0) return NBODY_OK;
   if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(mass, "mass")) ||
@@ -422,6 +457,7 @@ int nbody_accel_vjp_rows(int64_t n, int64_t row_begin, int64_t row_count,
                          size_t ws_bytes, void *stream) {
   int rc;
   if ((rc = check_common(n, p, precision, false))) return rc;
+  precision = nbody::effective_precision(precision, n);
   if ((rc = check_rows(n, row_begin, row_count))) return rc;
   if (row_count == 0) return NBODY_OK;
   if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(mass, "mass")) ||
@@ -457,6 +493,7 @@ int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
                int64_t ckpt_every, void *ws, size_t ws_bytes, void *stream) {
   int rc;
   if ((rc = check_common(n, p, precision, true))) return rc;
+  precision = nbody::effective_precision(precision, n);
   if (!valid_steps(steps))
     return fail(NBODY_ERR_INVALID_ARGUMENT, "steps = %lld outside [0, %lld]",
                 (long long)steps, (long long)NBODY_MAX_STEPS);
@@ -488,7 +525,7 @@ int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
   // Workspace layout: boxes | split partials | (small systems) positions.
   double *boxes = ws_boxes(ws);
   double *part = ws_parts(ws, box_bytes_fwd(n, precision));
-  const bool small = small_step(precision, n);
+  const bool small = nbody::small_system(precision, n);
   double *xbuf = small ? reinterpret_cast<double *>(
                              reinterpret_cast<char *>(part) +
                              dbytes(pl.sj * 3 * n))
@@ -546,6 +583,7 @@ int nbody_accel_vjp(int64_t n, const double *pos, const double *mass,
                     size_t ws_bytes, void *stream) {
   int rc;
   if ((rc = check_common(n, p, precision, false))) return rc;
+  precision = nbody::effective_precision(precision, n);
   if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(mass, "mass")) ||
       (rc = check_ptr(gacc, "gacc")) || (rc = check_ptr(gpos, "gpos")) ||
       (rc = check_ptr(gmass, "gmass")))
@@ -578,6 +616,7 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
                        double *gmass, void *ws, size_t ws_bytes, void *stream) {
   int rc;
   if ((rc = check_common(n, p, precision, true))) return rc;
+  precision = nbody::effective_precision(precision, n);
   if (flags & ~NBODY_HALF_KICK_DRIFT)
     return fail(NBODY_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x",
                 flags & ~NBODY_HALF_KICK_DRIFT);
@@ -645,7 +684,7 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
         (kdk ? unsigned(nbody::kClose) : 0u) | unsigned(nbody::kOpen);
     for (int64_t t = 1; t < k; ++t) {
       const double *xp = seg + size_t(t - 1) * q3;
-      if (small_step(precision, n)) {
+      if (nbody::small_system(precision, n)) {
         e = nbody::launch_step_small(precision, nn, xp, mass, eps2, G, v_ws,
                                      v_ws, seg + size_t(t) * q3, a_ws, nullptr,
                                      h, dt, fl, st);
@@ -691,6 +730,7 @@ int nbody_diagnostics(int64_t n, const double *pos, const double *vel,
                       double *out, void *ws, size_t ws_bytes, void *stream) {
   int rc;
   if ((rc = check_common(n, p, precision, false))) return rc;
+  precision = nbody::effective_precision(precision, n);
   if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(vel, "vel")) ||
       (rc = check_ptr(mass, "mass")) || (rc = check_ptr(out, "out")))
     return rc;

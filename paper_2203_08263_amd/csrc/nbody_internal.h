@@ -27,9 +27,17 @@ struct Plan {
 enum KernelKind { kAccel = 0, kVjp = 1, kPotential = 2 };
 
 // Plan for nt target rows against n source bodies; the one-argument form is
-// the whole system (nt = n).
+// the whole system (nt = n).  Force evaluations of a small system
+// (small_system) get one shape, R = 1, L = 64, one source split, so every
+// call that evaluates its forces sums in the same order as its one-launch
+// step; make_plan_general is the shape search without that rule.
+bool small_system(int precision, int64_t n);
+// NBODY_MIXED_NF / NBODY_MIXED_NF64 of a small system are evaluated as
+// NBODY_MIXED_D64 / NBODY_FP64 (every run near); other precisions unchanged.
+int effective_precision(int precision, int64_t n);
 Plan make_plan(KernelKind kind, int precision, int64_t n);
 Plan make_plan(KernelKind kind, int precision, int64_t nt, int64_t n);
+Plan make_plan_general(KernelKind kind, int precision, int64_t nt, int64_t n);
 
 // Targets are bodies row0 .. row0 + nt - 1 of the n-body system (pos is
 // [3][n]), sources all n bodies; plan from make_plan(kind, precision, nt, n).

@@ -529,6 +529,7 @@ __global__ __launch_bounds__(64) void diag_final_kernel(
     if (R_ == 1 && L_ == 1) { CALL(1, 1); }                                 \
     else if (R_ == 1 && L_ == 4) { CALL(1, 4); }                            \
     else if (R_ == 1 && L_ == 16) { CALL(1, 16); }                          \
+    else if (R_ == 1 && L_ == 64) { CALL(1, 64); }                          \
     else if (R_ == 2 && L_ == 1) { CALL(2, 1); }                            \
     else if (R_ == 2 && L_ == 4) { CALL(2, 4); }                            \
     else if (R_ == 2 && L_ == 16) { CALL(2, 16); }                          \

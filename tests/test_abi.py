@@ -279,31 +279,48 @@ def test_near_far_workspace_adds_box_scratch(B):
     def most(n):
         boxes = -(-n // 16) + -(-n // 4) + -(-n // 16)
         return (boxes * 48 + 255) // 256 * 256
-    for n in (1, 300, 16384, 262144):
-        for op in (B.NBODY_OP_ACCEL, B.NBODY_OP_VJP, B.NBODY_OP_STEP):
+    ops = (B.NBODY_OP_ACCEL, B.NBODY_OP_VJP, B.NBODY_OP_STEP)
+    for n in (16384, 262144):
+        for op in ops:
             nf = B.nbody_workspace_bytes(op, n, 10, 1, B.NBODY_MIXED_NF)
             mx = B.nbody_workspace_bytes(op, n, 10, 1, B.NBODY_MIXED)
-            if op == B.NBODY_OP_STEP and n <= 512:
-                # the mixed step loop of a small system keeps a second
-                # position array (one launch per step); the near / far one
-                # does not
-                mx -= (3 * n * 8 + 255) // 256 * 256
             assert 0 < nf - mx <= most(n) and (nf - mx) % 256 == 0, (op, n)
         adj_nf = B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, n, 50, 10, 3)
         adj_mx = B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, n, 50, 10, 1)
         assert 0 < adj_nf - adj_mx <= most(n)
         # rows: boxes over all n sources plus the target rows' own
-        r = B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, n, max(1, n // 8), 3)
-        assert r > B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, n, max(1, n // 8), 1)
+        r = B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, n, n // 8, 3)
+        assert r > B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, n, n // 8, 1)
         # the FP64-near variant has boxes too (its plan may use more lanes
         # per target, hence fewer splits and a different size)
-        for op in (B.NBODY_OP_ACCEL, B.NBODY_OP_VJP, B.NBODY_OP_STEP):
+        for op in ops:
             nf64 = B.nbody_workspace_bytes(op, n, 10, 1, B.NBODY_MIXED_NF64)
             assert 0 < nf64 and nf64 % 256 == 0
             assert nf64 <= B.nbody_workspace_bytes(op, n, 10, 1, B.NBODY_MIXED) + most(n)
         # the potential of the diagnostics uses the D64 arithmetic, no boxes
         assert (B.nbody_workspace_bytes(B.NBODY_OP_DIAGNOSTICS, n, 0, 1, 3)
                 == B.nbody_workspace_bytes(B.NBODY_OP_DIAGNOSTICS, n, 0, 1, 2))
+
+
+def test_small_systems_evaluate_near_far_as_all_near(B):
+    # up to 1024 bodies NBODY_MIXED_NF is NBODY_MIXED_D64 (every run near),
+    # up to 2048 NBODY_MIXED_NF64 is NBODY_FP64: same workspaces for every
+    # operation; above those sizes the near / far modes keep their boxes
+    ops = (B.NBODY_OP_ACCEL, B.NBODY_OP_VJP, B.NBODY_OP_STEP,
+           B.NBODY_OP_STEP_ADJOINT, B.NBODY_OP_DIAGNOSTICS)
+    for n in (1, 300, 1024, 2048):
+        for op in ops:
+            nf64 = B.nbody_workspace_bytes(op, n, 10, 3, B.NBODY_MIXED_NF64)
+            assert nf64 == B.nbody_workspace_bytes(op, n, 10, 3, B.NBODY_FP64), (op, n)
+            nf = B.nbody_workspace_bytes(op, n, 10, 3, B.NBODY_MIXED_NF)
+            d64 = B.nbody_workspace_bytes(op, n, 10, 3, B.NBODY_MIXED_D64)
+            if op == B.NBODY_OP_DIAGNOSTICS:   # the potential is D64 anyway
+                assert nf == d64
+            else:
+                assert (nf == d64) == (n <= 1024), (op, n)
+        for op in (B.NBODY_OP_ACCEL, B.NBODY_OP_VJP):
+            r64 = B.nbody_rows_workspace_bytes(op, n, max(1, n // 3), B.NBODY_MIXED_NF64)
+            assert r64 == B.nbody_rows_workspace_bytes(op, n, max(1, n // 3), B.NBODY_FP64)
 
 
 def test_morton_workspace_bytes(B):

@@ -37,7 +37,9 @@ def B():
 def test_graph_replay_rollout_and_adjoint(B, oracle, prec):
     say("graph replay", prec)
     dev = torch.device("cuda:0")
-    n, S, K = 1024, 20, 5
+    # FP64 at N = 1024 steps in one launch per step; the near / far mode
+    # needs more than 1024 bodies to split (below it is all near)
+    n, S, K = (1536 if prec == "mixed_nf" else 1024), 20, 5
     pos, vel, mass = inputs.uniform_cube(n, 1001)
     if prec == "mixed_nf":   # spatial order, so the far form is exercised too
         o = oracle.morton_order(pos)

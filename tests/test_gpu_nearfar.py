@@ -126,8 +126,39 @@ def test_nf64_random_order_is_fp64(B, dev, oracle, n):
     assert np.all(np.abs(N(gm) - rm) <= bm), "dL/dm"
 
 
+@pytest.mark.parametrize("n", [500, 1024, 2048])
+def test_small_systems_are_all_near(B, dev, oracle, n):
+    # up to 1024 bodies NBODY_MIXED_NF is NBODY_MIXED_D64, up to 2048
+    # NBODY_MIXED_NF64 is NBODY_FP64 (every run near; a launch-bound system
+    # gains nothing from the split): bitwise, for the force, the VJP and a
+    # rollout, even in Morton order where larger systems take far runs
+    say("small near / far", n)
+    pos, vel, mass = inputs.uniform_cube(n, 1450 + n)
+    o = oracle.morton_order(pos)
+    pos, vel, mass = pos[:, o].copy(), vel[:, o].copy(), mass[o].copy()
+    g = inputs.upstream_normal(n, 1460 + n)
+    P, V, M, Gt = T(pos, dev), T(vel, dev), T(mass, dev), T(g, dev)
+    pairs = [("mixed_nf64", "fp64")] + ([("mixed_nf", "mixed_d64")] if n <= 1024 else [])
+    for nf, ref in pairs:
+        assert np.array_equal(N(B.nbody_accel(P, M, 1.0, 1e-3, nf)),
+                              N(B.nbody_accel(P, M, 1.0, 1e-3, ref)))
+        for a, b in zip(B.nbody_accel_vjp(P, M, Gt, 1.0, 1e-3, nf),
+                        B.nbody_accel_vjp(P, M, Gt, 1.0, 1e-3, ref)):
+            assert np.array_equal(N(a), N(b))
+        out = []
+        for q in (nf, ref):
+            p, v, acc = P.clone(), V.clone(), torch.empty_like(P)
+            B.nbody_step(p, v, acc, M, 1.0, 1e-3, 1e-3, 5, q)
+            out.append((N(p), N(v), N(acc)))
+        for a, b in zip(*out):
+            assert np.array_equal(a, b)
+    if n > 1024:   # NF proper: its far runs differ from D64
+        assert not np.array_equal(N(B.nbody_accel(P, M, 1.0, 1e-3, "mixed_nf")),
+                                  N(B.nbody_accel(P, M, 1.0, 1e-3, "mixed_d64")))
+
+
 @pytest.mark.parametrize("prec", ["mixed_nf", "mixed_nf64"])
-@pytest.mark.parametrize("n", [2000, 16384])
+@pytest.mark.parametrize("n", [3000, 16384])
 def test_sorted_accel_and_vjp_vs_oracle(B, dev, oracle, n, prec):
     say(prec, "sorted", n)
     pos, _, mass = _sorted_cube(oracle, n, 1500 + n)
@@ -169,7 +200,7 @@ def test_sorted_rows_and_determinism(B, dev, oracle):
 
 @pytest.mark.parametrize("prec", ["mixed_nf", "mixed_nf64"])
 def test_sorted_rollout_and_adjoint_vs_oracle(B, dev, oracle, prec):
-    n, S, K = 2048, 6, 4
+    n, S, K = 2560, 6, 4     # above the all-near sizes of both modes
     say(prec, "rollout + adjoint", n)
     pos, vel, mass = _sorted_cube(oracle, n, 1800)
     gxT = inputs.upstream_normal(n, 1801)

@@ -233,6 +233,25 @@ def test_step_one_launch_loop_sizes(B, dev, oracle, prec, n, S):
         assert metrics.normwise(rec[6:9], as_) <= 1e-12
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed_d64", "mixed"])
+def test_time_reversibility(B, dev, prec):
+    # kick-drift-kick is time-reversible: S steps, velocities negated, S more
+    # steps (reusing the cached acceleration) return to the start up to
+    # rounding.  N = 512 Plummer sphere, 200 steps each way.
+    say("time reversal", prec)
+    n, S = 512, 200
+    pos, vel, mass = inputs.plummer(n, 5)
+    P, V, M = T(pos, dev), T(vel, dev), T(mass, dev)
+    A = torch.empty_like(P)
+    B.nbody_step(P, V, A, M, 1.0, 1e-2, 1e-3, S, prec)
+    V.neg_()
+    B.nbody_step(P, V, A, M, 1.0, 1e-2, 1e-3, S, prec, acc_valid=True)
+    ex = np.abs(N(P) - pos).max() / np.abs(pos).max()
+    ev = np.abs(-N(V) - vel).max() / np.abs(vel).max()
+    say("  x %.2e v %.2e" % (ex, ev))
+    assert ex <= 1e-13 and ev <= 1e-13
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_step_chaining_bitwise(B, dev, prec):
     say("chaining", prec)
