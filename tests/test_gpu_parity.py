@@ -253,6 +253,37 @@ def test_time_reversibility(B, dev, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_momentum_and_angular_momentum_conserved(B, dev, oracle, prec):
+    # pair forces are central and opposite, and kick-drift-kick preserves
+    # both momenta exactly in exact arithmetic: over 100 steps of an N = 2048
+    # Plummer sphere the FP64 path keeps them to rounding (the oracle: 2e-17
+    # and 4e-17 of sum m|v|, sum m|x||v|); the FP32-pair modes' forces are
+    # opposite only up to their error, so their drift is bounded by
+    # steps * dt * sum_i m_i (accel bound_i) (and |x| times that for L)
+    say("conservation", prec)
+    n, S, dt = 2048, 100, 1e-3
+    pos, vel, mass = inputs.plummer(n, 7)
+    P, V, M = T(pos, dev), T(vel, dev), T(mass, dev)
+    A = torch.empty_like(P)
+    B.nbody_step(P, V, A, M, 1.0, 1e-2, dt, S, prec)
+    x, v = N(P), N(V)
+    dP = np.linalg.norm((mass * v).sum(axis=1) - (mass * vel).sum(axis=1))
+    dL = np.linalg.norm((mass * np.cross(x.T, v.T).T).sum(axis=1)
+                        - (mass * np.cross(pos.T, vel.T).T).sum(axis=1))
+    sP = (mass * np.linalg.norm(vel, axis=0)).sum()
+    sL = (mass * np.linalg.norm(pos, axis=0) * np.linalg.norm(vel, axis=0)).sum()
+    say("  dP %.2e dL %.2e (relative)" % (dP / sP, dL / sL))
+    if prec == "fp64":
+        assert dP <= 1e-14 * sP and dL <= 1e-14 * sL
+    else:
+        ab = 2 * _tol.accel_bound(pos, mass, 1.0, 1e-2, prec)
+        bP = S * dt * (mass * ab).sum()
+        rmax = np.linalg.norm(pos, axis=0).max() * 1.1
+        assert dP <= bP + 1e-14 * sP
+        assert dL <= rmax * bP + 1e-14 * sL
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_step_chaining_bitwise(B, dev, prec):
     say("chaining", prec)
     n = 700
