@@ -112,6 +112,30 @@ def test_fp64_pair_within_ulps_across_scales(B, dev):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_vjp_golden_two_body(B, dev, prec):
+    # hand-derived closed form (tests/golden/two_body_pythagorean_vjp.txt)
+    from fractions import Fraction
+    import os
+    vals = {}
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "two_body_pythagorean_vjp.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            key, *rest = line.split()
+            vals[key] = np.array([float(Fraction(t)) for t in rest])
+    say("golden two-body vjp", prec)
+    pos = np.array([vals["x1"], vals["x2"]]).T.copy()
+    g = np.array([vals["g1"], vals["g2"]]).T.copy()
+    gx, gm = B.nbody_accel_vjp(T(pos, dev), T(vals["m"], dev), T(g, dev),
+                               float(vals["G"][0]), float(np.sqrt(vals["eps2"][0])),
+                               prec)
+    tol = 4e-15 if prec in ("fp64", "mixed_nf64") else 4e-6
+    np.testing.assert_allclose(N(gx)[:, 0], vals["dx1"], rtol=tol, atol=0)
+    np.testing.assert_allclose(N(gx)[:, 1], vals["dx2"], rtol=tol, atol=0)
+    np.testing.assert_allclose(N(gm), np.r_[vals["dm1"], vals["dm2"]], rtol=tol)
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_accel_edge_cases(B, dev, oracle, prec):
     say("edge cases", prec)
     # one body: exactly zero

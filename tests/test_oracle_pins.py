@@ -52,6 +52,28 @@ def test_golden_two_body_closed_form(oracle):
     assert abs(pot - vals["W"][0]) <= 4e-16
 
 
+def _golden(name):
+    vals = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            key, *rest = line.split()
+            vals[key] = [float(Fraction(t)) for t in rest]
+    return vals
+
+
+def test_golden_two_body_vjp_closed_form(oracle):
+    v = _golden("two_body_pythagorean_vjp.txt")
+    pos = np.array([v["x1"], v["x2"]]).T.copy()
+    mass = np.array(v["m"])
+    g = np.array([v["g1"], v["g2"]]).T.copy()
+    gx, gm = oracle.accel_vjp(pos, mass, g, v["G"][0], math.sqrt(v["eps2"][0]))
+    np.testing.assert_allclose(gx[:, 0], v["dx1"], rtol=1e-15, atol=1e-300)
+    np.testing.assert_allclose(gx[:, 1], v["dx2"], rtol=1e-15, atol=1e-300)
+    np.testing.assert_allclose(gm, v["dm1"] + v["dm2"], rtol=1e-15)
+
+
 def _decimal_accel(pos, mass, G, eps):
     getcontext().prec = 40
     n = mass.size
