@@ -128,6 +128,22 @@ def test_cube16384_rollout(B, dev, oracle, cube16384, prec):
         assert np.abs(x - xS).max() <= 4 * w.steps ** 2 * w.dt ** 2 * ab
 
 
+def test_cube16384_rollout_half_kick_drift_fp64(B, dev, oracle, cube16384):
+    # the paper's printed update at the full N = 16384 size, FP64, against
+    # the oracle's rollout of the same update
+    w, pos, vel, mass, _, _ = cube16384
+    say("workload", w.name, "fp64 half-kick + drift rollout")
+    xS, vS, _ = oracle.step(pos, vel, mass, w.G, w.eps, w.dt, w.steps,
+                            scheme="half_kick_drift")
+    P, V, M = T(pos, dev), T(vel, dev), T(mass, dev)
+    A = torch.empty_like(P)
+    B.nbody_step(P, V, A, M, w.G, w.eps, w.dt, w.steps, "fp64",
+                 integrator="half_kick_drift")
+    ex, ev = metrics.normwise(N(P), xS), metrics.normwise(N(V), vS)
+    say("  final state err x %.2e v %.2e" % (ex, ev))
+    assert ex <= 1e-12 and ev <= 1e-12
+
+
 # ---------------------------------------- N = 65536 Plummer, mixed, 10 steps --
 
 @pytest.mark.parametrize("prec", PRECS)
