@@ -422,3 +422,15 @@ def test_step_counts_and_sizes_cannot_overflow(B):
     rc = lib.nbody_step_f32(100, max_steps + 1, _p(FAKE), _p(FAKE), _p(FAKE), _p(FAKE),
                             _params(B), 0, _p(FAKE), 1 << 40, None)
     assert rc == 1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: bench.py --gpus 2 exits with a message, before touching
+    # torch or the GPU
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr
