@@ -135,6 +135,13 @@ enum nbody_op {
   NBODY_OP_MORTON_SORT = 5
 };
 
+/* Smallest softening length accepted by every precision other than
+ * NBODY_FP64 (2^-42): their FP32 pair arithmetic evaluates the self pair with
+ * weight m eps^-3, so eps^2 must be a normal FP32 number and eps^-3 finite in
+ * FP32.  The masses must also keep m_j * eps^-3 below FLT_MAX (3.4e38), which
+ * the library cannot check on the host (masses live in device memory). */
+#define NBODY_MIN_EPS_FP32 (0x1p-42)
+
 /* Largest supported body count. */
 #define NBODY_MAX_N ((int64_t)1 << 28)
 
@@ -165,8 +172,9 @@ size_t nbody_checkpoint_bytes(int64_t n, int64_t steps, int64_t ckpt_every);
  *  ws   device   scratch of ws_bytes >= nbody_workspace_bytes(NBODY_OP_ACCEL)
  *                (may be NULL when that is 0)
  * Errors: INVALID_ARGUMENT (n outside [1, NBODY_MAX_N], NULL pointer,
- * non-finite G/eps, eps <= 0, unknown precision, misaligned pointer),
- * WORKSPACE_TOO_SMALL, HIP (launch failure; see nbody_last_error). */
+ * non-finite G/eps, eps <= 0, eps < NBODY_MIN_EPS_FP32 or FP32 eps^2 infinite
+ * for a precision other than NBODY_FP64, unknown precision, misaligned
+ * pointer), WORKSPACE_TOO_SMALL, HIP (launch failure; see nbody_last_error). */
 int nbody_accel(int64_t n, const double *pos, const double *mass, double *acc,
                 const nbody_params *p, int precision, void *ws,
                 size_t ws_bytes, void *stream);

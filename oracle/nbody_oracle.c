@@ -32,8 +32,8 @@
  *    scheme 1.
  *
  * Parity pins: tests/test_oracle_pins.py checks every function here against
- * closed forms, a 40-digit decimal brute force, an independent NumPy
- * broadcasting form, invariants and central finite differences.
+ * closed forms, a 40-digit decimal brute force, an independent whole-matrix
+ * NumPy form, invariants and central finite differences.
  */
 #include <math.h>
 #include <stdint.h>

@@ -393,9 +393,12 @@ def nbody_accel_vjp_rows(pos, mass, gacc, row_begin, row_count, G=1.0, eps=1e-3,
     return gpos, gmass
 
 
-def nbody_morton_sort(pos, mass, vel=None, workspace=None):
+def nbody_morton_sort(pos, mass, vel=None, workspace=None, perm=None,
+                      pos_out=None, vel_out=None, mass_out=None):
     """Bodies in Morton (Z) order of their positions: returns (perm, pos_out,
-    vel_out or None, mass_out) with pos_out[:, r] = pos[:, perm[r]]."""
+    vel_out or None, mass_out) with pos_out[:, r] = pos[:, perm[r]].  `vel`
+    may be any (3, n) per-body vector carried along with the bodies (e.g.
+    dL/da).  Outputs are allocated unless given."""
     lib = load_library()
     n = mass.shape[0]
     dev = mass.device
@@ -403,11 +406,21 @@ def nbody_morton_sort(pos, mass, vel=None, workspace=None):
     _vec(pos, n, "pos", dev)
     if vel is not None:
         _vec(vel, n, "vel", dev)
-    perm = torch.empty(n, dtype=torch.int64, device=dev)
-    pos_out = torch.empty((3, n), dtype=torch.float64, device=dev)
-    vel_out = None if vel is None else torch.empty((3, n), dtype=torch.float64,
-                                                   device=dev)
-    mass_out = torch.empty(n, dtype=torch.float64, device=dev)
+    if perm is None:
+        perm = torch.empty(n, dtype=torch.int64, device=dev)
+    elif (perm.dtype != torch.int64 or tuple(perm.shape) != (n,)
+          or not perm.is_contiguous() or perm.device != dev):
+        raise ValueError("perm must be a contiguous int64 (%d,) tensor on %s" % (n, dev))
+    pos_out = torch.empty((3, n), dtype=torch.float64, device=dev) if pos_out is None \
+        else _vec(pos_out, n, "pos_out", dev)
+    if vel is None:
+        if vel_out is not None:
+            raise ValueError("vel_out given without vel")
+    else:
+        vel_out = torch.empty((3, n), dtype=torch.float64, device=dev) \
+            if vel_out is None else _vec(vel_out, n, "vel_out", dev)
+    mass_out = torch.empty(n, dtype=torch.float64, device=dev) if mass_out is None \
+        else _scal(mass_out, n, "mass_out", dev)
     ws, wsb = _workspace(lib.nbody_workspace_bytes(NBODY_OP_MORTON_SORT, n, 0, 1, 0),
                          dev, workspace)
     _run(dev, lib.nbody_morton_sort, n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(perm),

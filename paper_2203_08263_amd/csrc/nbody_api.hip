@@ -159,6 +159,18 @@ int check_common(int64_t n, const nbody_params *p, int precision,
     return fail(NBODY_ERR_INVALID_ARGUMENT, "dt is not finite");
   if (!valid_precision(precision))
     return fail(NBODY_ERR_INVALID_ARGUMENT, "unknown precision %d", precision);
+  // Every precision but NBODY_FP64 evaluates pairs in FP32, the self pair
+  // (d = 0) included: its weight m eps^-3 multiplies d = 0, which gives 0 only
+  // while eps^2 is a normal FP32 number (not flushed to 0) and eps^-3 is
+  // finite in FP32; otherwise every output would be NaN.
+  if (precision != NBODY_FP64) {
+    const float e2 = float(p->eps * p->eps);
+    if (!(p->eps >= NBODY_MIN_EPS_FP32) || !isfinite(e2))
+      return fail(NBODY_ERR_INVALID_ARGUMENT,
+                  "eps = %g outside the FP32 pair range [%g, 1.8e19] of "
+                  "precision %d",
+                  p->eps, NBODY_MIN_EPS_FP32, precision);
+  }
   return NBODY_OK;
 }
 

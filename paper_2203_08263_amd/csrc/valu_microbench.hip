@@ -31,16 +31,19 @@
 constexpr int kThreads = 256;
 constexpr int kChains = 8;
 
-template <int OP, typename T>
+template <int OP, typename T, int NCH = kChains, bool VOPS = false>
 __global__ __launch_bounds__(kThreads) void chains(int iters, T seed,
                                                    T *__restrict__ out) {
-  T a[kChains];
-  const T b = seed * T(0.999), c = seed * T(1e-3);
+  T a[NCH];
+  // VOPS: per-thread multiplier and addend (VGPR operands) instead of
+  // wave-uniform ones (scalar registers)
+  const T t = VOPS ? T(threadIdx.x) * T(1e-6) : T(0);
+  const T b = seed * T(0.999) + t, c = seed * T(1e-3) + t;
 #pragma unroll
-  for (int k = 0; k < kChains; ++k) a[k] = seed + T(threadIdx.x + k);
+  for (int k = 0; k < NCH; ++k) a[k] = seed + T(threadIdx.x + k);
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
-    for (int k = 0; k < kChains; ++k) {
+    for (int k = 0; k < NCH; ++k) {
       if constexpr (OP == 0) a[k] = fma(a[k], b, c);          // fma
       if constexpr (OP == 1) a[k] = a[k] * b;                  // mul
       if constexpr (OP == 2) a[k] = a[k] + c;                  // add
@@ -52,8 +55,63 @@ __global__ __launch_bounds__(kThreads) void chains(int iters, T seed,
   }
   T s = 0;
 #pragma unroll
-  for (int k = 0; k < kChains; ++k) s += a[k];
+  for (int k = 0; k < NCH; ++k) s += a[k];
   out[blockIdx.x * kThreads + threadIdx.x] = s;
+}
+
+// The forward pair's operation mix, NCH independent pairs per thread and
+// iteration: 3 sub, 3 FMA (r^2 + eps^2), v_rsq_f32, 3 mul, 3 FMA into
+// per-chain accumulators -- exactly 13 operations per pair.  Each chain's
+// next source is its own accumulator (no memory traffic, nothing the
+// compiler can hoist out of the loop).  Thread 0 of every workgroup records
+// the shader-clock counter (clock64) and the constant-rate counter
+// (wall_clock64) at its start and end into stamp[4 * blockIdx.x ...], so the
+// host can derive the clock the chip ran at under this load.
+template <int NCH>
+__global__ __launch_bounds__(kThreads) void pair_mix(int iters, float seed,
+                                                     float *__restrict__ out,
+                                                     unsigned long long *stamp) {
+  unsigned long long c0 = 0, w0 = 0;
+  if (threadIdx.x == 0) {
+    c0 = clock64();
+    w0 = wall_clock64();
+  }
+  const float xi = seed * float(threadIdx.x) * 1e-3f;
+  const float yi = -xi, zi = 0.5f * xi, eps2 = 1e-6f;
+  float ax[NCH], ay[NCH], az[NCH];
+#pragma unroll
+  for (int k = 0; k < NCH; ++k) {
+    ax[k] = 0.25f + float(k);
+    ay[k] = -0.5f;
+    az[k] = 0.75f - float(k);
+  }
+  const float m = 1e-4f;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+      const float dx = ax[k] - xi, dy = ay[k] - yi, dz = az[k] - zi;
+      float s = fmaf(dx, dx, eps2);
+      s = fmaf(dy, dy, s);
+      s = fmaf(dz, dz, s);
+      const float y = __builtin_amdgcn_rsqf(s);
+      const float w = (m * y) * (y * y);
+      ax[k] = fmaf(w, dx, ax[k]);
+      ay[k] = fmaf(w, dy, ay[k]);
+      az[k] = fmaf(w, dz, az[k]);
+    }
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int k = 0; k < NCH; ++k) r += ax[k] + ay[k] + az[k];
+  out[blockIdx.x * kThreads + threadIdx.x] = r;
+  if (threadIdx.x == 0) {
+    const unsigned long long c1 = clock64(), w1 = wall_clock64();
+    unsigned long long *o = stamp + 4 * size_t(blockIdx.x);
+    o[0] = c0;
+    o[1] = c1;
+    o[2] = w0;
+    o[3] = w1;
+  }
 }
 
 // 12 FMAs and one v_rsq_f32 per chain and iteration.
@@ -178,6 +236,57 @@ int main(int argc, char **argv) {
   report("v_rsq_f64", time_ms([&] { chains<3, double><<<blocks, kThreads, 0, st>>>(iters, 1.0, d); }, st), 1);
   report("fma_f32_x12_plus_rsq_f32 (per op)",
          time_ms([&] { fma12_rsq1<<<blocks, kThreads, 0, st>>>(iters, 1.0f, f); }, st), 13);
+  report("v_fma_f32, 16 chains",
+         time_ms([&] { chains<0, float, 16><<<blocks, kThreads, 0, st>>>(iters / 2, 1.0f, f); }, st), 1);
+  report("v_fma_f32, 8 chains, VGPR operands",
+         time_ms([&] { chains<0, float, 8, true><<<blocks, kThreads, 0, st>>>(iters, 1.0f, f); }, st), 1);
+  report("v_add_f32, 16 chains",
+         time_ms([&] { chains<2, float, 16><<<blocks, kThreads, 0, st>>>(iters / 2, 1.0f, f); }, st), 1);
+  report("v_rsq_f32, 16 chains",
+         time_ms([&] { chains<3, float, 16><<<blocks, kThreads, 0, st>>>(iters / 2, 1.0f, f); }, st), 1);
+
+  // The forward pair mix (13 operations per pair) with 4, 8 and 16
+  // independent pairs per thread, and the shader clock it ran at.
+  int wall_khz = 0;
+  CHECK(hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev));
+  unsigned long long *stamp = nullptr;
+  CHECK(hipMalloc(&stamp, size_t(4) * blocks * sizeof(unsigned long long)));
+  unsigned long long *hs = static_cast<unsigned long long *>(
+      malloc(size_t(4) * blocks * sizeof(unsigned long long)));
+  if (!hs) return 1;
+  auto mix = [&](const char *name, double ms, int nch) {
+    CHECK(hipMemcpy(hs, stamp, size_t(4) * blocks * sizeof(unsigned long long),
+                    hipMemcpyDeviceToHost));
+    double cyc = 0.0, wall = 0.0, fmin = 1e30, fmax = 0.0;
+    for (int b = 0; b < blocks; ++b) {
+      const double dc = double(hs[4 * b + 1] - hs[4 * b]);
+      const double dw = double(hs[4 * b + 3] - hs[4 * b + 2]);
+      cyc += dc;
+      wall += dw;
+      if (dw > 0) {
+        const double fb = dc / dw * wall_khz * 1e-6;
+        fmin = fb < fmin ? fb : fmin;
+        fmax = fb > fmax ? fb : fmax;
+      }
+    }
+    const double ghz = wall > 0 ? cyc / wall * wall_khz * 1e-6 : 0.0;
+    const double pairs = double(nthreads) * (iters / (nch / 4)) * nch;
+    const double pps = pairs / (ms * 1e-3);
+    printf("{\"op\": \"%s\", \"ms\": %.4f, \"pairs_per_s\": %.4e, "
+           "\"pairs_per_cu_per_clk_at_2.4GHz\": %.3f, \"clock64_ghz_mean\": %.3f, "
+           "\"clock64_ghz_min\": %.3f, \"clock64_ghz_max\": %.3f, "
+           "\"wall_clock_khz\": %d}\n",
+           name, ms, pps, pps / (cus * 2.4e9), ghz, fmin, fmax, wall_khz);
+    fflush(stdout);
+  };
+  mix("pair_mix_f32, 4 pairs per thread",
+      time_ms([&] { pair_mix<4><<<blocks, kThreads, 0, st>>>(iters, 1.0f, f, stamp); }, st), 4);
+  mix("pair_mix_f32, 8 pairs per thread",
+      time_ms([&] { pair_mix<8><<<blocks, kThreads, 0, st>>>(iters / 2, 1.0f, f, stamp); }, st), 8);
+  mix("pair_mix_f32, 16 pairs per thread",
+      time_ms([&] { pair_mix<16><<<blocks, kThreads, 0, st>>>(iters / 4, 1.0f, f, stamp); }, st), 16);
+  free(hs);
+  CHECK(hipFree(stamp));
   report("cvt_f32_f64+cvt_f64_f32+mul_f64 (per op)",
          time_ms([&] { cvt_chain<<<blocks, kThreads, 0, st>>>(iters, 1.0, d); }, st), 3);
 

@@ -27,6 +27,8 @@ These are worst-case bounds; the measured errors sit far below them.
 """
 from __future__ import annotations
 
+import hashlib
+
 import numpy as np
 
 U32 = 2.0 ** -24
@@ -60,28 +62,113 @@ def _rows_iter(rows, n):
         yield rows[s:s + block]
 
 
+# Every bound below is a fixed linear combination of a few sums over the
+# source bodies that do not depend on the precision (only u, the chunk length
+# and the coordinate perturbation delta do).  Those O(rows * n) sums are
+# computed once per input and kept, so bounds for several precisions of the
+# same system (e.g. 1024 rows of a 262144-body system) cost one pass.
+_SUMS_CACHE = {}
+
+
+def _key(*parts):
+    h = hashlib.blake2b(digest_size=16)
+    for p in parts:
+        a = np.ascontiguousarray(p)
+        h.update(str(a.shape).encode())
+        h.update(str(a.dtype).encode())
+        h.update(a.tobytes())
+    return h.hexdigest()
+
+
+def _cached(kind, fn, *parts):
+    key = (kind, _key(*parts))
+    if key not in _SUMS_CACHE:
+        if len(_SUMS_CACHE) > 64:
+            _SUMS_CACHE.clear()
+        _SUMS_CACHE[key] = fn()
+    return _SUMS_CACHE[key]
+
+
+def accel_sums(pos, mass, eps, rows):
+    """Per row i (self pair left out), with w = m_j s^-3/2 and dn = |d_ij|:
+    S0 = sum w, S1 = sum w dn, S2 = sum w |x_j|; and |x_i|."""
+    n = mass.size
+
+    def compute():
+        xn = np.linalg.norm(pos, axis=0)
+        out = np.empty((4, len(rows)))
+        k = 0
+        for blk in _rows_iter(rows, n):
+            d = pos[:, None, :] - pos[:, blk, None]             # (3, b, n)
+            dn = np.sqrt((d * d).sum(axis=0))
+            s = dn * dn + eps * eps
+            w = mass[None, :] / (s * np.sqrt(s))
+            w[np.arange(len(blk)), blk] = 0.0                   # self pair: exactly 0
+            out[0, k:k + len(blk)] = w.sum(axis=1)
+            out[1, k:k + len(blk)] = (w * dn).sum(axis=1)
+            out[2, k:k + len(blk)] = (w * xn[None, :]).sum(axis=1)
+            out[3, k:k + len(blk)] = xn[blk]
+            k += len(blk)
+        return out
+    return _cached("accel", compute, pos, mass, np.float64(eps), rows)
+
+
 def accel_bound(pos, mass, G, eps, precision, rows=None):
-    """Bound on |a_i^gpu - a_i| (Euclidean) for each row i."""
+    """Bound on |a_i^gpu - a_i| (Euclidean) for each row i:
+    SAFETY * |G| * sum_j w_ij (4 delta_ij + (16 + L) u |d_ij|)."""
     n = mass.size
     rows = np.arange(n) if rows is None else np.asarray(rows)
-    xn = np.linalg.norm(pos, axis=0)
-    out = np.empty(len(rows))
+    S0, S1, S2, xi = accel_sums(pos, mass, eps, rows)
     if precision == "fp64":
-        u, L = U64, n + 64
+        arith = (16 + n + 64) * U64 * S1
+        pert = 0.0
     else:
-        u, L = U32, CHUNK32
-    k = 0
-    for blk in _rows_iter(rows, n):
-        d = pos[:, None, :] - pos[:, blk, None]             # (3, b, n)
-        dn = np.sqrt((d * d).sum(axis=0))
-        s = dn * dn + eps * eps
-        w = mass[None, :] * s ** -1.5
-        delta = _delta(precision, xn, blk, dn)
-        term = w * (4.0 * delta + (16 + L) * u * dn)
-        term[np.arange(len(blk)), blk] = 0.0          # self pair: exactly 0
-        out[k:k + len(blk)] = abs(G) * term.sum(axis=1)
-        k += len(blk)
-    return SAFETY * out
+        arith = (16 + CHUNK32) * U32 * S1
+        if precision == "mixed":
+            pert = 4.0 * U32 * (xi * S0 + S2 + S1)
+        elif precision == "mixed_d64":
+            pert = 4.0 * U32 * S1
+        elif precision in ("mixed_nf", "mixed_nf64"):
+            pert = 4.0 * NF_DELTA * U32 * S1
+        else:
+            raise ValueError(precision)
+    return SAFETY * abs(G) * (pert + arith)
+
+
+def vjp_sums(pos, mass, gacc, eps, rows):
+    """Per row k (self pair left out), with y3 = s^-3/2, r = s^-1/2 and
+    e = |x_j - x_k|: the sums over j of y3 |g_j| f and y3 m_j f for
+    f in {1, e r, |x_j| r, r}, of y3 |g_j| f for f in {e, |x_j|}, and the
+    row's own m_k, |g_k|, |x_k|."""
+    n = mass.size
+
+    def compute():
+        xn = np.linalg.norm(pos, axis=0)
+        gn = np.linalg.norm(gacc, axis=0)
+        out = np.empty((13, len(rows)))
+        k = 0
+        for blk in _rows_iter(rows, n):
+            e = pos[:, None, :] - pos[:, blk, None]
+            en = np.sqrt((e * e).sum(axis=0))
+            s = en * en + eps * eps
+            r = 1.0 / np.sqrt(s)
+            y3 = r * r * r
+            y3[np.arange(len(blk)), blk] = 0.0                  # self pair: e = h = 0
+            yg = y3 * gn[None, :]
+            ym = y3 * mass[None, :]
+            fs = (1.0, en * r, xn[None, :] * r, r)
+            sl = slice(k, k + len(blk))
+            for c, f in enumerate(fs):
+                out[c, sl] = (yg * f).sum(axis=1)
+                out[4 + c, sl] = (ym * f).sum(axis=1)
+            out[8, sl] = (yg * en).sum(axis=1)
+            out[9, sl] = (yg * xn[None, :]).sum(axis=1)
+            out[10, sl] = mass[blk]
+            out[11, sl] = gn[blk]
+            out[12, sl] = xn[blk]
+            k += len(blk)
+        return out
+    return _cached("vjp", compute, pos, mass, gacc, np.float64(eps), rows)
 
 
 def vjp_bound(pos, mass, gacc, G, eps, precision, rows=None):
@@ -100,32 +187,33 @@ def vjp_bound(pos, mass, gacc, G, eps, precision, rows=None):
     u * eps^-3 * u * m_k |g_k| per row (added below)."""
     n = mass.size
     rows = np.arange(n) if rows is None else np.asarray(rows)
-    xn = np.linalg.norm(pos, axis=0)
-    gn = np.linalg.norm(gacc, axis=0)
-    bx = np.empty(len(rows))
-    bm = np.empty(len(rows))
+    v = vjp_sums(pos, mass, gacc, eps, rows)
+    mk, gk, xk = v[10], v[11], v[12]
+    # sums of A f with A = y3 H = m_k (y3 |g_j|) + |g_k| (y3 m_j)
+    A = [mk * v[c] + gk * v[4 + c] for c in range(4)]     # f = 1, e r, |x_j| r, r
+    Bsum, Be, Bx = v[0], v[8], v[9]                       # y3 |g_j| times 1, e, |x_j|
     if precision == "fp64":
         u, L = U64, n + 64
     else:
         u, L = U32, VJP_CHUNK32
-    k = 0
-    for blk in _rows_iter(rows, n):
-        e = pos[:, None, :] - pos[:, blk, None]
-        en = np.sqrt((e * e).sum(axis=0))
-        s = en * en + eps * eps
-        y3 = s ** -1.5
-        H = mass[blk, None] * gn[None, :] + mass[None, :] * gn[blk, None]
-        delta = _delta(precision, xn, blk, en)
-        tx = y3 * H * (12.0 * delta / np.sqrt(s) + (40 + L) * u * 4.0)
-        tm = y3 * gn[None, :] * (4.0 * delta + (16 + L) * u * en)
-        # self pair: e = 0 and h = 0 exactly in the kernels
-        tx[np.arange(len(blk)), blk] = 0.0
-        tm[np.arange(len(blk)), blk] = 0.0
-        self_res = u * eps ** -3 * u * mass[blk] * gn[blk]
-        bx[k:k + len(blk)] = abs(G) * (tx.sum(axis=1) + self_res)
-        bm[k:k + len(blk)] = abs(G) * tm.sum(axis=1)
-        k += len(blk)
-    return SAFETY * bx, SAFETY * bm
+    ax = 4.0 * (40 + L) * u * A[0]
+    am = (16 + L) * u * Be
+    if precision == "fp64":
+        px = pm = 0.0
+    elif precision == "mixed":
+        px = 12.0 * U32 * (xk * A[3] + A[2] + A[1])
+        pm = 4.0 * U32 * (xk * Bsum + Bx + Be)
+    elif precision == "mixed_d64":
+        px = 12.0 * U32 * A[1]
+        pm = 4.0 * U32 * Be
+    elif precision in ("mixed_nf", "mixed_nf64"):
+        px = 12.0 * NF_DELTA * U32 * A[1]
+        pm = 4.0 * NF_DELTA * U32 * Be
+    else:
+        raise ValueError(precision)
+    self_res = u * eps ** -3 * u * mk * gk
+    return (SAFETY * abs(G) * (px + ax + self_res),
+            SAFETY * abs(G) * (pm + am))
 
 
 def adjoint_bound(oracle, pos, vel, mass, G, eps, dt, steps, gx, gv, ga,

@@ -196,6 +196,45 @@ def test_vjp_and_adjoint_reject_invalid_arguments(B):
     assert adj(wsb=ws - 256) == 2
 
 
+@pytest.mark.parametrize("prec", [1, 2, 3, 4])
+@pytest.mark.parametrize("eps", [1e-14, 2.0 ** -42 * 0.999, 1e-30, 1e20])
+def test_fp32_pair_modes_reject_eps_outside_fp32_range(B, prec, eps):
+    """Every precision but FP64 evaluates the self pair in FP32 with weight
+    m eps^-3: an eps whose FP32 eps^2 flushes to 0 or whose eps^-3 overflows
+    would make every output NaN, so the host rejects it before any launch
+    (accel, VJP, step and adjoint alike); FP64 accepts the same eps."""
+    lib = B.load_library()
+    n = 1000
+    assert _accel(B, n=n, prec=prec, eps=eps, ws=FAKE, wsb=1 << 30) == 1
+    assert "FP32 pair range" in lib.nbody_last_error().decode()
+    assert lib.nbody_accel_vjp(n, _p(FAKE), _p(FAKE), _p(FAKE), _p(FAKE), _p(FAKE),
+                               _params(B, eps=eps), prec, _p(FAKE), 1 << 30, None) == 1
+    assert lib.nbody_step(n, 1, _p(FAKE), _p(FAKE), _p(FAKE), _p(FAKE),
+                          _params(B, eps=eps), prec, 0, None, 1, _p(FAKE), 1 << 30,
+                          None) == 1
+    assert lib.nbody_step_adjoint(n, 10, 5, _p(FAKE), _p(FAKE), _params(B, eps=eps),
+                                  prec, 0, _p(FAKE), _p(FAKE), None, _p(FAKE),
+                                  _p(FAKE), 1 << 30, None) == 1
+    assert lib.nbody_accel_rows(n, 0, 10, _p(FAKE), _p(FAKE), _p(FAKE),
+                                _params(B, eps=eps), prec, _p(FAKE), 1 << 30,
+                                None) == 1
+    assert "FP32 pair range" in lib.nbody_last_error().decode()
+    if eps < 1e19:
+        # FP64 accepts this eps and fails only later, on the missing workspace
+        # (n = 65536 needs one, so nothing is launched)
+        assert _accel(B, n=65536, prec=0, eps=eps, ws=None, wsb=0) == 2
+
+
+def test_fp32_pair_modes_accept_the_smallest_eps(B):
+    lib = B.load_library()
+    txt = open(HEADER).read()
+    assert "#define NBODY_MIN_EPS_FP32 (0x1p-42)" in txt
+    # passes the eps check, then fails on the missing workspace
+    for prec in (1, 2, 3, 4):
+        rc = _accel(B, n=65536, prec=prec, eps=2.0 ** -42, ws=None, wsb=0)
+        assert rc == 2, lib.nbody_last_error().decode()
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     from paper_2203_08263_amd import binding
     monkeypatch.setattr(binding, "_lib", None)

@@ -3,9 +3,10 @@
 Each test ties one oracle routine to something the mathematics or the
 physics fixes: hand-derived closed forms (tests/golden), a 40-digit decimal
 brute force, the potential whose negative gradient the acceleration must be,
-an independent NumPy form shaped like the paper's broadcasting listing
-(section 3.1), conservation laws and orbit closed forms for the integrator,
-and central finite differences / torch autograd for the derivatives.
+an independent whole-matrix NumPy form (all N x N pair differences at once,
+contracted with einsum), conservation laws and orbit closed forms for the
+integrator, and central finite differences / torch autograd for the
+derivatives.
 """
 import math
 import os
@@ -154,26 +155,23 @@ def test_accel_is_minus_gradient_of_potential(oracle):
             assert mass[i] * a[c, i] == pytest.approx(-dW, rel=1e-7, abs=1e-9)
 
 
-def _numpy_broadcast_accel(pos, mass, G, eps):
-    """Independent form shaped like the paper's CPython broadcasting listing
-    (section 3.1): per target i, vectorised over sources, force G m_i m_j
-    d s^-1.5 summed, then divided by m_i.  AoS (n, 3) layout."""
-    P = pos.T.copy()
-    soft = eps * eps
-    out = np.empty_like(P)
-    for i in range(P.shape[0]):
-        dpos = np.subtract(P, P[i])
-        dsq = (dpos ** 2.0).sum(axis=1) + soft
-        gm = mass * (mass[i] * G)
-        forces = np.multiply((gm * dsq ** -1.5).reshape(-1, 1), dpos).sum(axis=0)
-        out[i] = forces / mass[i]
-    return out.T
+def _pairwise_tensor_accel(pos, mass, G, eps):
+    """Independent whole-matrix form of the section 2.3 force: the difference
+    tensor D[c, i, j] = x_j - x_i of all N x N pairs at once, the softened
+    inverse cube K[i, j] = (|D_ij|^2 + eps^2)^(-3/2), the pair forces
+    G m_i m_j K_ij D_ij contracted over the sources j in one einsum, then
+    divided by the target masses m_i (force first, as the paper forms it,
+    rather than the oracle's acceleration-first sum)."""
+    D = pos[:, None, :] - pos[:, :, None]
+    K = (np.einsum("cij,cij->ij", D, D) + eps * eps) ** -1.5
+    F = G * np.einsum("i,j,ij,cij->ci", mass, mass, K, D)
+    return F / mass[None, :]
 
 
-def test_accel_vs_numpy_broadcasting_form(oracle):
+def test_accel_vs_pairwise_tensor_form(oracle):
     pos, _, mass = inputs.uniform_cube(400, 77)
     a = oracle.accel(pos, mass, 1.0, 1e-3)
-    ref = _numpy_broadcast_accel(pos, mass, 1.0, 1e-3)
+    ref = _pairwise_tensor_accel(pos, mass, 1.0, 1e-3)
     bound = 64 * np.finfo(float).eps * _abs_force_sum(pos, mass, 1.0, 1e-3)
     assert np.all(np.abs(a - ref) <= bound[None, :])
 
