@@ -21,7 +21,8 @@
  *    torch tensor on the same device), 8-byte aligned, unless the comment
  *    says "host".  The caller owns all buffers, including the workspace and
  *    checkpoint buffers; the library never allocates or frees device memory
- *    and keeps no device state between calls.  Input and output arrays of one
+ *    and keeps no device state between calls (one exception:
+ *    nbody_accel_noalloc's static scratch array).  Input and output arrays of one
  *    call must not overlap unless the comment says "in/out".
  *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  All work
  *    is enqueued on it and the call returns without synchronising; a fault
@@ -178,6 +179,30 @@ size_t nbody_checkpoint_bytes(int64_t n, int64_t steps, int64_t ckpt_every);
 int nbody_accel(int64_t n, const double *pos, const double *mass, double *acc,
                 const nbody_params *p, int precision, void *ws,
                 size_t ws_bytes, void *stream);
+
+/* nbody_accel without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same kernels, launch plan and
+ * result -- bitwise -- as nbody_accel, with the split partial sums and the
+ * near / far box scratch in a static array of NBODY_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) that the library holds on every device it runs this call on until
+ * the process ends (its device address is looked up once per device, on the
+ * first call there).  The call allocates and frees nothing.  All calls on one
+ * device share that array: calls that overlap in time on one device (two
+ * streams, two host threads) race and must be serialised by the caller.
+ * Arguments as nbody_accel, minus the workspace; `stream`'s device (the
+ * current device for NULL) selects the array.
+ * Errors: as nbody_accel; WORKSPACE_TOO_SMALL, before anything is enqueued,
+ * when nbody_workspace_bytes(NBODY_OP_ACCEL, n, 0, 1, precision) exceeds
+ * NBODY_NOALLOC_SCRATCH_BYTES.  Every n below 932068 fits for NBODY_MIXED
+ * and NBODY_MIXED_D64, below 681739 for NBODY_MIXED_NF, below 14913073 for
+ * NBODY_MIXED_NF64 and below 65025 for NBODY_FP64 (larger n only where
+ * that workspace happens to fit).  UNSUPPORTED for a device index of 64 or
+ * more. */
+#define NBODY_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int nbody_accel_noalloc(int64_t n, const double *pos, const double *mass,
+                        double *acc, const nbody_params *p, int precision,
+                        void *stream);
 
 /* `steps` kick-drift-kick leapfrog steps, in place (the paper's step loop of
  * section 2.3 with its two dependencies; the integrator is KDK):

@@ -34,13 +34,14 @@ NBODY_OP_ACCEL, NBODY_OP_STEP, NBODY_OP_VJP, NBODY_OP_STEP_ADJOINT = 0, 1, 2, 3
 NBODY_OP_DIAGNOSTICS = 4
 NBODY_OP_MORTON_SORT = 5
 NBODY_MAX_N = 1 << 28
+NBODY_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 SYMBOLS = ("nbody_workspace_bytes", "nbody_checkpoint_bytes", "nbody_accel",
            "nbody_step", "nbody_accel_vjp", "nbody_step_adjoint",
            "nbody_diagnostics", "nbody_rows_workspace_bytes",
            "nbody_accel_rows", "nbody_accel_vjp_rows", "nbody_morton_sort",
            "nbody_f32_workspace_bytes", "nbody_accel_f32", "nbody_step_f32",
-           "nbody_error_string", "nbody_last_error")
+           "nbody_accel_noalloc", "nbody_error_string", "nbody_last_error")
 
 _INVALID = ctypes.c_size_t(-1).value
 
@@ -81,6 +82,7 @@ def load_library():
     lib.nbody_checkpoint_bytes.argtypes = [i64, i64, i64]
     lib.nbody_checkpoint_bytes.restype = sz
     lib.nbody_accel.argtypes = [i64, vp, vp, vp, pp, ci, vp, sz, vp]
+    lib.nbody_accel_noalloc.argtypes = [i64, vp, vp, vp, pp, ci, vp]
     lib.nbody_step.argtypes = [i64, i64, vp, vp, vp, vp, pp, ci, ctypes.c_uint,
                                vp, i64, vp, sz, vp]
     lib.nbody_accel_vjp.argtypes = [i64, vp, vp, vp, vp, vp, pp, ci, vp, sz, vp]
@@ -98,7 +100,7 @@ def load_library():
     lib.nbody_accel_f32.argtypes = [i64, vp, vp, vp, pp, vp, sz, vp]
     lib.nbody_step_f32.argtypes = [i64, i64, vp, vp, vp, vp, pp, ctypes.c_uint, vp,
                                    sz, vp]
-    for f in ("nbody_accel", "nbody_step", "nbody_accel_vjp",
+    for f in ("nbody_accel", "nbody_accel_noalloc", "nbody_step", "nbody_accel_vjp",
               "nbody_step_adjoint", "nbody_diagnostics", "nbody_accel_rows",
               "nbody_accel_vjp_rows", "nbody_morton_sort", "nbody_accel_f32",
               "nbody_step_f32"):
@@ -220,6 +222,24 @@ def nbody_accel(pos, mass, G=1.0, eps=1e-3, precision=NBODY_FP64, out=None,
     prm = _Params(G, eps, 0.0)
     _run(dev, lib.nbody_accel, n, _ptr(pos), _ptr(mass), _ptr(acc), ctypes.byref(prm),
          prec, _ptr(ws), wsb, _stream(dev))
+    return acc
+
+
+def nbody_accel_noalloc(pos, mass, G=1.0, eps=1e-3, precision=NBODY_FP64, out=None):
+    """nbody_accel without a workspace: the library's static device scratch
+    holds the partial sums (the call allocates nothing; `out` must be given
+    by callers that cannot allocate)."""
+    lib = load_library()
+    n = mass.shape[0]
+    dev = mass.device
+    _scal(mass, n, "mass")
+    _vec(pos, n, "pos", dev)
+    prec = _precision(precision)
+    acc = torch.empty((3, n), dtype=torch.float64, device=dev) if out is None \
+        else _vec(out, n, "out", dev)
+    prm = _Params(G, eps, 0.0)
+    _run(dev, lib.nbody_accel_noalloc, n, _ptr(pos), _ptr(mass), _ptr(acc),
+         ctypes.byref(prm), prec, _stream(dev))
     return acc
 
 

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <utility>
 
 #include "../../include/nbody.h"
@@ -344,6 +345,89 @@ int accel_to_parts(const Plan &pl, int prec, int n, const double *pos,
   return e == hipSuccess ? NBODY_OK : hip_fail(e, "accel kernel launch");
 }
 
+// Argument checks of nbody_accel (everything but the workspace).
+int check_accel_args(int64_t n, const double *pos, const double *mass,
+                     const double *acc, const nbody_params *p, int precision) {
+  int rc;
+  if ((rc = check_common(n, p, precision, false))) return rc;
+  if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(mass, "mass")) ||
+      (rc = check_ptr(acc, "acc")))
+    return rc;
+  return NBODY_OK;
+}
+
+// The force evaluation of nbody_accel once its arguments are checked:
+// precision is already the effective one and ws holds ws_accel(n, precision)
+// bytes.  Box scratch | split partials, then the split reduction (scaled by
+// G); a single split writes acc directly.
+int accel_enqueue(int64_t n, const double *pos, const double *mass,
+                  double *acc, const nbody_params *p, int precision, void *ws,
+                  hipStream_t st) {
+  const int nn = int(n);
+  const double eps2 = p->eps * p->eps;
+  const Plan pl = nbody::make_plan(nbody::kAccel, precision, n);
+  double *boxes = ws_boxes(ws);
+  hipError_t e;
+  if (pl.sj == 1) {
+    e = run_accel(pl, precision, nn, 0, nn, pos, mass, boxes, eps2, p->G, acc,
+                  0, st);
+    return e == hipSuccess ? NBODY_OK : hip_fail(e, "accel kernel launch");
+  }
+  double *part = ws_parts(ws, box_bytes_fwd(n, precision));
+  int rc;
+  if ((rc = accel_to_parts(pl, precision, nn, pos, mass, boxes, eps2, part,
+                           st)))
+    return rc;
+  e = nbody::launch_reduce(nn, int(pl.sj), part, size_t(3) * n, p->G, acc,
+                           nullptr, st);
+  return e == hipSuccess ? NBODY_OK : hip_fail(e, "reduce kernel launch");
+}
+
+// ---- Static scratch of nbody_accel_noalloc (for callers that cannot
+// allocate device memory).  The array is zero-initialised device memory of
+// the code object: every GPU the library runs this entry point on holds its
+// own copy, at its own address, until the process ends.  In host code
+// `scratch` names a host-side stand-in, never the device memory: its device
+// address is taken once per device with hipGetSymbolAddress (that device
+// current) and only that address is passed to kernels.  Calls on one device
+// share the array, so calls that overlap in time on one device (two streams,
+// two threads) race; nothing in it has to start at zero (the box scratch and
+// the split partials are written in full before they are read).
+constexpr size_t kStaticScratchBytes = NBODY_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// The device address of the stream's device's copy of `scratch`.
+int static_scratch(hipStream_t st, void **out) {
+  int cur = -1, dev = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  dev = cur;
+  if (st) {
+    e = hipStreamGetDevice(st, &dev);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamGetDevice");
+  }
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(NBODY_ERR_UNSUPPORTED, "device %d beyond the %d the static "
+                "scratch table covers", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess)
+      return hip_fail(e, "hipSetDevice");
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    const hipError_t e2 = dev != cur ? hipSetDevice(cur) : hipSuccess;
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipSetDevice");
+    if (!ptr) return fail(NBODY_ERR_HIP, "hipGetSymbolAddress(scratch) gave NULL");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return NBODY_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -401,31 +485,30 @@ int nbody_accel(int64_t n, const double *pos, const double *mass, double *acc,
                 const nbody_params *p, int precision, void *ws,
                 size_t ws_bytes, void *stream) {
   int rc;
-  if ((rc = check_common(n, p, precision, false))) return rc;
+  if ((rc = check_accel_args(n, pos, mass, acc, p, precision))) return rc;
   precision = nbody::effective_precision(precision, n);
-  if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(mass, "mass")) ||
-      (rc = check_ptr(acc, "acc")))
-    return rc;
   if ((rc = check_ws(ws, ws_bytes, ws_accel(n, precision)))) return rc;
+  return accel_enqueue(n, pos, mass, acc, p, precision, ws,
+                       static_cast<hipStream_t>(stream));
+}
+
+int nbody_accel_noalloc(int64_t n, const double *pos, const double *mass,
+                        double *acc, const nbody_params *p, int precision,
+                        void *stream) {
+  int rc;
+  if ((rc = check_accel_args(n, pos, mass, acc, p, precision))) return rc;
+  precision = nbody::effective_precision(precision, n);
+  const size_t need = ws_accel(n, precision);
+  if (need > kStaticScratchBytes)
+    return fail(NBODY_ERR_WORKSPACE_TOO_SMALL,
+                "n = %lld, precision %d needs %zu bytes of scratch; the "
+                "library's static scratch holds %zu (use nbody_accel with a "
+                "workspace)",
+                (long long)n, precision, need, kStaticScratchBytes);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int nn = int(n);
-  const double eps2 = p->eps * p->eps;
-  const Plan pl = nbody::make_plan(nbody::kAccel, precision, n);
-  double *boxes = ws_boxes(ws);
-  hipError_t e;
-  if (pl.sj == 1) {
-    e = run_accel(pl, precision, nn, 0, nn, pos, mass, boxes, eps2, p->G, acc,
-                  0, st);
-    if (e != hipSuccess) return hip_fail(e, "accel kernel launch");
-    return NBODY_OK;
-  }
-  double *part = ws_parts(ws, box_bytes_fwd(n, precision));
-  if ((rc = accel_to_parts(pl, precision, nn, pos, mass, boxes, eps2, part,
-                           st)))
-    return rc;
-  e = nbody::launch_reduce(nn, int(pl.sj), part, size_t(3) * n, p->G, acc,
-                           nullptr, st);
-  return e == hipSuccess ? NBODY_OK : hip_fail(e, "reduce kernel launch");
+  void *ws = nullptr;
+  if (need > 0 && (rc = static_scratch(st, &ws))) return rc;
+  return accel_enqueue(n, pos, mass, acc, p, precision, ws, st);
 }
 
 int nbody_accel_rows(int64_t n, int64_t row_begin, int64_t row_count,

@@ -156,6 +156,50 @@ def test_accel_workspace_too_small(B):
     assert _accel(B, n=n, ws=0, wsb=need) == 1  # NULL workspace
 
 
+def _accel_noalloc(B, n=64, pos=FAKE, mass=FAKE, acc=FAKE, prec=0, **kw):
+    lib = B.load_library()
+    return lib.nbody_accel_noalloc(n, _p(pos), _p(mass), _p(acc), _params(B, **kw),
+                                   prec, None)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(n=0), "outside"), (dict(pos=0), "pos is NULL"), (dict(acc=0), "acc is NULL"),
+    (dict(mass=FAKE + 4), "aligned"), (dict(eps=0.0), "eps"),
+    (dict(prec=1, eps=1e-14), "FP32 pair range"), (dict(prec=7), "precision"),
+])
+def test_accel_noalloc_rejects_invalid_arguments(B, kw, msg):
+    assert _accel_noalloc(B, **kw) == 1
+    assert msg in B.load_library().nbody_last_error().decode()
+
+
+# (n, precision) whose nbody_accel workspace exceeds the static scratch: the
+# first size over it for each precision, and the largest workspaces of the
+# FP32-pair modes (2 source splits of just under 2^21 bodies).
+@pytest.mark.parametrize("n,prec", [(65025, 0), (262144, 0), (932068, 1), (2096891, 1),
+                                    (932068, 2), (681739, 3), (14913073, 4)])
+def test_accel_noalloc_rejects_sizes_beyond_its_scratch(B, n, prec):
+    need = B.nbody_workspace_bytes(B.NBODY_OP_ACCEL, n, 0, 1, prec)
+    assert need > B.NBODY_NOALLOC_SCRATCH_BYTES
+    assert _accel_noalloc(B, n=n, prec=prec) == 2
+    assert "static scratch" in B.load_library().nbody_last_error().decode()
+
+
+def test_accel_noalloc_limits_match_the_header(B):
+    """The sizes the header says fit: every n below the stated first
+    failures (checked on a grid of n plus the neighbours of each limit)."""
+    lim = B.NBODY_NOALLOC_SCRATCH_BYTES
+    txt = open(HEADER).read()
+    assert re.search(r"NBODY_NOALLOC_SCRATCH_BYTES \(\(size_t\)64 << 20\)", txt)
+    assert lim == 64 << 20
+    first = {0: 65025, 1: 932068, 2: 932068, 3: 681739, 4: 14913073}
+    for prec, nf in first.items():
+        assert B.nbody_workspace_bytes(B.NBODY_OP_ACCEL, nf, 0, 1, prec) > lim
+        grid = sorted(set(list(range(1, min(nf, 70000), 97)) + [nf - 1, nf - 2, nf - 255]
+                          + list(range(1, nf, max(1, nf // 3000)))))
+        for n in grid:
+            assert B.nbody_workspace_bytes(B.NBODY_OP_ACCEL, n, 0, 1, prec) <= lim, (prec, n)
+
+
 def test_step_rejects_invalid_arguments(B):
     lib = B.load_library()
     pr = _params(B)
