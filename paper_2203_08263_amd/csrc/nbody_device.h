@@ -16,6 +16,7 @@ namespace {
 
 constexpr int kChunk = 32;        // FP32 sources per FP64 flush (forward)
 constexpr int kVjpChunk = 16;     // FP32 sources per FP64 flush (VJP)
+constexpr int kPairBatch = 8;     // FP32 pair weights formed ahead of their sums
 constexpr int kBodyThreads = 64;  // threads per workgroup, per-body kernels
 
 // -------------------------------------------------------------- arithmetic --
@@ -64,6 +65,40 @@ __device__ __forceinline__ void pair_f32(float dx, float dy, float dz, float m,
   ax = fmaf(w, dx, ax);
   ay = fmaf(w, dy, ay);
   az = fmaf(w, dz, az);
+}
+
+// The FP32 pair terms of the C sources u = 0 .. C-1 of one chunk, added in
+// ascending u into (fx, fy, fz); src(u, dx, dy, dz, m) yields source u's
+// difference x_j - x_i and mass in FP32.  The weights of B sources are formed
+// before their terms are added: B independent pair chains for the scheduler
+// (one source at a time, the compiler waits on each LDS read before its
+// pair).  The additions keep the ascending order, so the sums are bitwise
+// those of pair_f32 applied source by source.
+template <int C, int B, typename SrcF>
+__device__ __forceinline__ void chunk_sum_f32(SrcF src, float eps2, float &fx,
+                                              float &fy, float &fz) {
+  constexpr int BB = B < C ? B : C;
+  static_assert(C % BB == 0, "chunk length must be a multiple of the batch");
+#pragma unroll
+  for (int u0 = 0; u0 < C; u0 += BB) {
+    float dx[BB], dy[BB], dz[BB], w[BB];
+#pragma unroll
+    for (int q = 0; q < BB; ++q) {
+      float m;
+      src(u0 + q, dx[q], dy[q], dz[q], m);
+      float s = fmaf(dx[q], dx[q], eps2);
+      s = fmaf(dy[q], dy[q], s);
+      s = fmaf(dz[q], dz[q], s);
+      const float y = rsqrt_f32(s);
+      w[q] = (m * y) * (y * y);
+    }
+#pragma unroll
+    for (int q = 0; q < BB; ++q) {
+      fx = fmaf(w[q], dx[q], fx);
+      fy = fmaf(w[q], dy[q], fy);
+      fz = fmaf(w[q], dz[q], fz);
+    }
+  }
 }
 
 // One source j against target k for the VJP (row formulation):

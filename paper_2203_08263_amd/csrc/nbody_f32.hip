@@ -51,11 +51,17 @@ __global__ __launch_bounds__(kThreads) void accel_f32_kernel(
     __syncthreads();
     tile[tid] = b;
     __syncthreads();
-#pragma unroll 16
-    for (int u = 0; u < PER; ++u) {
-      const Src<NBODY_MIXED> s = tile[u * L + q];
-      pair_f32(s.x - xi, s.y - yi, s.z - zi, s.m, eps2, ax, ay, az);
-    }
+    constexpr int U = PER < 16 ? PER : 16;  // sources per unrolled step
+    for (int u0 = 0; u0 < PER; u0 += U)
+      chunk_sum_f32<U, kPairBatch>(
+          [&](int u, float &dx, float &dy, float &dz, float &m) {
+            const Src<NBODY_MIXED> s = tile[(u0 + u) * L + q];
+            dx = s.x - xi;
+            dy = s.y - yi;
+            dz = s.z - zi;
+            m = s.m;
+          },
+          eps2, ax, ay, az);
   }
   float *o = out + size_t(blockIdx.y) * split_stride;
   const float sx = group_sum_f<L>(ax);

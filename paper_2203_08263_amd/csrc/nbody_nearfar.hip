@@ -37,6 +37,10 @@ constexpr int kBodyThreadsSort = 256;
 // bitwise those of NBODY_MIXED_D64.
 
 constexpr double kNearFarKappa2 = 0.25;  // kappa = 1/2
+// FP32 far-run sources whose weights are formed ahead of their sums
+// (chunk_sum_f32): 4 keeps the forward kernels within 64 VGPRs (8 waves per
+// SIMD), which 8 would not.
+constexpr int kNfFarBatch = 4;
 
 // FP32 sources per chunk sum, and so per near / far decision, of each kernel
 // (per lane; a run of the tile is C*L consecutive sources).  The forward of
@@ -301,18 +305,25 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
       }
       float fx = 0.0f, fy = 0.0f, fz = 0.0f;
       if (far) {
-#pragma unroll
-        for (int u = 0; u < C; ++u) {
-          const Src<NBODY_MIXED> s = far_tile[(u0 + u) * L + q];
-          pair_f32(s.x - xr, s.y - yr, s.z - zr, s.m, eps2, fx, fy, fz);
-        }
+        chunk_sum_f32<C, kNfFarBatch>(
+            [&](int u, float &dx, float &dy, float &dz, float &m) {
+              const Src<NBODY_MIXED> s = far_tile[(u0 + u) * L + q];
+              dx = s.x - xr;
+              dy = s.y - yr;
+              dz = s.z - zr;
+              m = s.m;
+            },
+            eps2, fx, fy, fz);
       } else if constexpr (!NEAR64) {
-#pragma unroll
-        for (int u = 0; u < C; ++u) {
-          const NearSrc s = near_tile[(u0 + u) * L + q];
-          pair_f32(float(s.x - xi), float(s.y - yi), float(s.z - zi), float(s.m),
-                   eps2, fx, fy, fz);
-        }
+        chunk_sum_f32<C, 1>(
+            [&](int u, float &dx, float &dy, float &dz, float &m) {
+              const NearSrc s = near_tile[(u0 + u) * L + q];
+              dx = float(s.x - xi);
+              dy = float(s.y - yi);
+              dz = float(s.z - zi);
+              m = float(s.m);
+            },
+            eps2, fx, fy, fz);
       }
       ax += double(fx);
       ay += double(fy);
