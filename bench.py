@@ -61,8 +61,9 @@ FLOPS_PER_PAIR = {"accel": 20, "vjp": 48, "diag": 13}
 DTYPE = {"fp64": "f64", "mixed": "f32-pair/f64-acc",
          "mixed_d64": "f32-pair(f64-diff)/f64-acc",
          "mixed_nf": "f32-pair(near f64-diff, far recentred)/f64-acc",
-         "mixed_nf64": "near f64-pair, far f32-pair(recentred)/f64-acc"}
-PRECS = ("fp64", "mixed", "mixed_d64", "mixed_nf", "mixed_nf64")
+         "mixed_nf64": "near f64-pair, far f32-pair(recentred)/f64-acc",
+         "mixed_ds": "f32-pair(two-float diff)/f64-acc"}
+PRECS = ("fp64", "mixed", "mixed_d64", "mixed_nf", "mixed_nf64", "mixed_ds")
 SORTED = ("mixed_nf", "mixed_nf64")   # run on the bodies in Morton order
 KERNEL_KIND = {"accel": "accel_kernel", "vjp": "vjp_kernel"}
 # HBM bytes per launch of a roofline kernel from two rocprofv3 --pmc runs

@@ -60,7 +60,7 @@ typedef struct nbody_params {
 } nbody_params;
 
 /* Arithmetic of the pair force.  State, accumulation across source tiles,
- * the integrator and every output are FP64 in all three.
+ * the integrator and every output are FP64 in every precision.
  *  NBODY_FP64       every operation in FP64.
  *  NBODY_MIXED      positions and masses rounded to FP32; pair difference,
  *                   r^2 + eps^2, reciprocal square root, cube and the
@@ -94,16 +94,25 @@ typedef struct nbody_params {
  *                   FP64 throughout; a system of at most 2048 bodies is
  *                   evaluated exactly as NBODY_FP64.  nbody_diagnostics
  *                   evaluates W in FP64.
+ *  NBODY_MIXED_DS   as NBODY_MIXED, but every coordinate v is carried as two
+ *                   FP32 numbers, hi = fl32(v) and lo = fl32(v - hi), and
+ *                   the pair difference is (x_j^hi - x_i^hi) +
+ *                   (x_j^lo - x_i^lo) in FP32 (the first difference is exact
+ *                   for close pairs): coordinate error per pair at most
+ *                   about 2 u32 |x_j - x_i| + 4 u32^2 (|x_i| + |x_j|), with
+ *                   no FP64 operation in the pair (the two-float reading of
+ *                   the paper's float32 / float64 comparison, section 4).
  * Every force evaluation of a small system (NBODY_FP64 up to 2048 bodies,
- * NBODY_MIXED_D64 up to 1024, NBODY_MIXED up to 512) sums in one order,
- * whether it comes from nbody_accel, the row-range form or nbody_step, whose
- * loop then takes one launch per step. */
+ * NBODY_MIXED_D64 and NBODY_MIXED_DS up to 1024, NBODY_MIXED up to 512) sums
+ * in one order, whether it comes from nbody_accel, the row-range form or
+ * nbody_step, whose loop then takes one launch per step. */
 enum nbody_precision {
   NBODY_FP64 = 0,
   NBODY_MIXED = 1,
   NBODY_MIXED_D64 = 2,
   NBODY_MIXED_NF = 3,
-  NBODY_MIXED_NF64 = 4
+  NBODY_MIXED_NF64 = 4,
+  NBODY_MIXED_DS = 5
 };
 
 enum nbody_status {
@@ -194,11 +203,11 @@ int nbody_accel(int64_t n, const double *pos, const double *mass, double *acc,
  * current device for NULL) selects the array.
  * Errors: as nbody_accel; WORKSPACE_TOO_SMALL, before anything is enqueued,
  * when nbody_workspace_bytes(NBODY_OP_ACCEL, n, 0, 1, precision) exceeds
- * NBODY_NOALLOC_SCRATCH_BYTES.  Every n below 932068 fits for NBODY_MIXED
- * and NBODY_MIXED_D64, below 681739 for NBODY_MIXED_NF, below 14913073 for
- * NBODY_MIXED_NF64 and below 65025 for NBODY_FP64 (larger n only where
- * that workspace happens to fit).  UNSUPPORTED for a device index of 64 or
- * more. */
+ * NBODY_NOALLOC_SCRATCH_BYTES.  Every n below 932068 fits for NBODY_MIXED,
+ * NBODY_MIXED_D64 and NBODY_MIXED_DS, below 681739 for NBODY_MIXED_NF, below
+ * 14913073 for NBODY_MIXED_NF64 and below 65025 for NBODY_FP64 (larger n
+ * only where that workspace happens to fit).  UNSUPPORTED for a device index
+ * of 64 or more. */
 #define NBODY_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 int nbody_accel_noalloc(int64_t n, const double *pos, const double *mass,
                         double *acc, const nbody_params *p, int precision,

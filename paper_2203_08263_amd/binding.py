@@ -22,9 +22,10 @@ NBODY_MIXED = 1
 NBODY_MIXED_D64 = 2
 NBODY_MIXED_NF = 3
 NBODY_MIXED_NF64 = 4
+NBODY_MIXED_DS = 5
 PRECISIONS = {"fp64": NBODY_FP64, "mixed": NBODY_MIXED,
               "mixed_d64": NBODY_MIXED_D64, "mixed_nf": NBODY_MIXED_NF,
-              "mixed_nf64": NBODY_MIXED_NF64}
+              "mixed_nf64": NBODY_MIXED_NF64, "mixed_ds": NBODY_MIXED_DS}
 
 NBODY_OK = 0
 NBODY_ACC_VALID = 1

@@ -36,7 +36,8 @@ namespace nbody {
 bool small_system(int precision, int64_t n) {
   switch (precision) {
     case NBODY_FP64: return n <= 2048;
-    case NBODY_MIXED_D64: return n <= 1024;
+    case NBODY_MIXED_D64:
+    case NBODY_MIXED_DS: return n <= 1024;
     case NBODY_MIXED: return n <= 512;
     default: return false;
   }
@@ -138,7 +139,7 @@ size_t dbytes(int64_t count) { return round_up(size_t(count) * sizeof(double)); 
 
 bool valid_precision(int p) {
   return p == NBODY_FP64 || p == NBODY_MIXED || p == NBODY_MIXED_D64 ||
-         p == NBODY_MIXED_NF || p == NBODY_MIXED_NF64;
+         p == NBODY_MIXED_NF || p == NBODY_MIXED_NF64 || p == NBODY_MIXED_DS;
 }
 
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }

@@ -17,6 +17,7 @@ namespace {
 constexpr int kChunk = 32;        // FP32 sources per FP64 flush (forward)
 constexpr int kVjpChunk = 16;     // FP32 sources per FP64 flush (VJP)
 constexpr int kPairBatch = 8;     // FP32 pair weights formed ahead of their sums
+constexpr int kDsBatch = 4;       // the same for two-float differences
 constexpr int kBodyThreads = 64;  // threads per workgroup, per-body kernels
 
 // -------------------------------------------------------------- arithmetic --
@@ -148,10 +149,30 @@ __device__ __forceinline__ double self_pair_term(T mk, T gk, T eps2) {
 
 // ------------------------------------------------------ source tile layout --
 
+// NBODY_MIXED_DS splits a coordinate v into two FP32 numbers, hi = fl32(v)
+// and lo = fl32(v - hi) (v - hi is exact in FP64), so hi + lo carries v to
+// within u32^2 |v|.  The pair difference is then formed as
+// (x_j^hi - x_i^hi) + (x_j^lo - x_i^lo) in FP32: the first difference is
+// exact for close pairs (Sterbenz), the second is of order u32 |x| and
+// rounds at the u32^2 level, so d carries about 2 u32 |d| + 4 u32^2
+// (|x_i| + |x_j|) instead of the u32 (|x_i| + |x_j|) of rounding the
+// positions themselves.
+__device__ __forceinline__ void split_f32(double v, float &hi, float &lo) {
+  hi = float(v);
+  lo = float(v - double(hi));
+}
+
+__device__ __forceinline__ float ds_diff(float sh, float sl, float th,
+                                         float tl) {
+  return (sh - th) + (sl - tl);
+}
+
 template <int PREC> struct Src;
 template <> struct Src<NBODY_FP64> { double x, y, z, m; };
 template <> struct Src<NBODY_MIXED> { float x, y, z, m; };
 template <> struct Src<NBODY_MIXED_D64> { double x, y, z; float m, pad; };
+// x, y, z: the hi parts; xl, yl, zl: the lo parts
+template <> struct Src<NBODY_MIXED_DS> { float x, y, z, m, xl, yl, zl, pad; };
 
 template <int PREC>
 __device__ __forceinline__ Src<PREC> load_src(const double *__restrict__ pos,
@@ -159,9 +180,15 @@ __device__ __forceinline__ Src<PREC> load_src(const double *__restrict__ pos,
                                               int n, int j, bool valid) {
   Src<PREC> b{};
   if (valid) {
-    b.x = pos[j];
-    b.y = pos[n + j];
-    b.z = pos[2 * n + j];
+    if constexpr (PREC == NBODY_MIXED_DS) {
+      split_f32(pos[j], b.x, b.xl);
+      split_f32(pos[n + j], b.y, b.yl);
+      split_f32(pos[2 * n + j], b.z, b.zl);
+    } else {
+      b.x = pos[j];
+      b.y = pos[n + j];
+      b.z = pos[2 * n + j];
+    }
     b.m = mass[j];   // rounds to FP32 in the mixed modes
   }
   return b;
@@ -174,11 +201,16 @@ template <> struct VSrc<NBODY_MIXED_D64> {
   double x, y, z;
   float m, gx, gy, gz, pad0, pad1;
 };
+template <> struct VSrc<NBODY_MIXED_DS> {
+  float x, y, z, m, gx, gy, gz, pad0, xl, yl, zl, pad1;
+};
 
-// Coordinate type of a target body and of its pair difference.
+// Coordinate type of a target body and of its pair difference (for
+// NBODY_MIXED_DS the type of each of the two parts).
 template <int PREC> struct Coord { using T = double; using D = double; };
 template <> struct Coord<NBODY_MIXED> { using T = float; using D = float; };
 template <> struct Coord<NBODY_MIXED_D64> { using T = double; using D = float; };
+template <> struct Coord<NBODY_MIXED_DS> { using T = float; using D = float; };
 
 // Sum over the L consecutive lanes that share a target (L a power of two
 // dividing the wave size) by an xor butterfly: every stage adds the same two

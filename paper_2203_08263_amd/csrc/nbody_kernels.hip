@@ -60,14 +60,21 @@ __device__ __forceinline__ void accel_lane_sums(
   const int ibase = blockIdx.x * (G * R) + g;
 
   CT xi[R], yi[R], zi[R];
+  float xl[R], yl[R], zl[R];  // lo parts (NBODY_MIXED_DS only)
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = ibase + r * G;
     const bool ok = i < nt;
     const int gi = row0 + i;
-    xi[r] = ok ? CT(pos[gi]) : CT(0);
-    yi[r] = ok ? CT(pos[n + gi]) : CT(0);
-    zi[r] = ok ? CT(pos[2 * n + gi]) : CT(0);
+    if constexpr (PREC == NBODY_MIXED_DS) {
+      split_f32(ok ? pos[gi] : 0.0, xi[r], xl[r]);
+      split_f32(ok ? pos[n + gi] : 0.0, yi[r], yl[r]);
+      split_f32(ok ? pos[2 * n + gi] : 0.0, zi[r], zl[r]);
+    } else {
+      xi[r] = ok ? CT(pos[gi]) : CT(0);
+      yi[r] = ok ? CT(pos[n + gi]) : CT(0);
+      zi[r] = ok ? CT(pos[2 * n + gi]) : CT(0);
+    }
     ax[r] = ay[r] = az[r] = 0.0;
   }
 
@@ -105,6 +112,27 @@ __device__ __forceinline__ void accel_lane_sums(
         ax[0] += double(fx);
         ay[0] += double(fy);
         az[0] += double(fz);
+      }
+    } else if constexpr (PREC == NBODY_MIXED_DS) {
+      // two-float differences (ds_diff), then the FP32 pair of NBODY_MIXED
+      const float eps2 = float(eps2d);
+      for (int u0 = 0; u0 < PER; u0 += C) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+          chunk_sum_f32<C, kDsBatch>(
+              [&](int u, float &dx, float &dy, float &dz, float &m) {
+                const Src<PREC> s = tile[(u0 + u) * L + q];
+                dx = ds_diff(s.x, s.xl, xi[r], xl[r]);
+                dy = ds_diff(s.y, s.yl, yi[r], yl[r]);
+                dz = ds_diff(s.z, s.zl, zi[r], zl[r]);
+                m = s.m;
+              },
+              eps2, fx, fy, fz);
+          ax[r] += double(fx);
+          ay[r] += double(fy);
+          az[r] += double(fz);
+        }
       }
     } else {
       // FP64 sources (difference rounded once): batching would hold the FP64
@@ -188,6 +216,7 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
   const int jend = min(n, jbeg + jchunk);
 
   CT xk[R], yk[R], zk[R];
+  float xl[R], yl[R], zl[R];  // lo parts (NBODY_MIXED_DS only)
   AT mk[R], gkx[R], gky[R], gkz[R];
   double sx[R], sy[R], sz[R], sm[R];
 #pragma unroll
@@ -195,9 +224,15 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
     const int k = kbase + r * G;
     const bool ok = k < nt;
     const int gk = row0 + k;
-    xk[r] = ok ? CT(pos[gk]) : CT(0);
-    yk[r] = ok ? CT(pos[n + gk]) : CT(0);
-    zk[r] = ok ? CT(pos[2 * n + gk]) : CT(0);
+    if constexpr (PREC == NBODY_MIXED_DS) {
+      split_f32(ok ? pos[gk] : 0.0, xk[r], xl[r]);
+      split_f32(ok ? pos[n + gk] : 0.0, yk[r], yl[r]);
+      split_f32(ok ? pos[2 * n + gk] : 0.0, zk[r], zl[r]);
+    } else {
+      xk[r] = ok ? CT(pos[gk]) : CT(0);
+      yk[r] = ok ? CT(pos[n + gk]) : CT(0);
+      zk[r] = ok ? CT(pos[2 * n + gk]) : CT(0);
+    }
     mk[r] = ok ? AT(mass[gk]) : AT(0);
     gkx[r] = ok ? AT(gacc[gk]) : AT(0);
     gky[r] = ok ? AT(gacc[n + gk]) : AT(0);
@@ -209,9 +244,15 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
     const int j = jt + tid;
     VSrc<PREC> b{};
     if (j < jend) {
-      b.x = pos[j];
-      b.y = pos[n + j];
-      b.z = pos[2 * n + j];
+      if constexpr (PREC == NBODY_MIXED_DS) {
+        split_f32(pos[j], b.x, b.xl);
+        split_f32(pos[n + j], b.y, b.yl);
+        split_f32(pos[2 * n + j], b.z, b.zl);
+      } else {
+        b.x = pos[j];
+        b.y = pos[n + j];
+        b.z = pos[2 * n + j];
+      }
       b.m = mass[j];
       b.gx = gacc[j];
       b.gy = gacc[n + j];
@@ -241,10 +282,20 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
         for (int u = 0; u < C; ++u) {
           const VSrc<PREC> s = tile[(u0 + u) * L + q];
 #pragma unroll
-          for (int r = 0; r < R; ++r)
-            vjp_pair<float>(DT(s.x - xk[r]), DT(s.y - yk[r]), DT(s.z - zk[r]),
-                            s.m, s.gx, s.gy, s.gz, mk[r], gkx[r], gky[r],
-                            gkz[r], eps2, fx[r], fy[r], fz[r], fm[r]);
+          for (int r = 0; r < R; ++r) {
+            float ex, ey, ez;
+            if constexpr (PREC == NBODY_MIXED_DS) {
+              ex = ds_diff(s.x, s.xl, xk[r], xl[r]);
+              ey = ds_diff(s.y, s.yl, yk[r], yl[r]);
+              ez = ds_diff(s.z, s.zl, zk[r], zl[r]);
+            } else {
+              ex = DT(s.x - xk[r]);
+              ey = DT(s.y - yk[r]);
+              ez = DT(s.z - zk[r]);
+            }
+            vjp_pair<float>(ex, ey, ez, s.m, s.gx, s.gy, s.gz, mk[r], gkx[r],
+                            gky[r], gkz[r], eps2, fx[r], fy[r], fz[r], fm[r]);
+          }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -313,9 +364,17 @@ __global__ __launch_bounds__(kThreads) void potential_kernel(
   const int jbeg = blockIdx.y * jchunk;
   const int jend = min(n, jbeg + jchunk);
   const bool ok = i < n;
-  const CT xi = ok ? CT(pos[i]) : CT(0);
-  const CT yi = ok ? CT(pos[n + i]) : CT(0);
-  const CT zi = ok ? CT(pos[2 * n + i]) : CT(0);
+  CT xi, yi, zi;
+  float xl = 0.0f, yl = 0.0f, zl = 0.0f;  // lo parts (NBODY_MIXED_DS only)
+  if constexpr (PREC == NBODY_MIXED_DS) {
+    split_f32(ok ? pos[i] : 0.0, xi, xl);
+    split_f32(ok ? pos[n + i] : 0.0, yi, yl);
+    split_f32(ok ? pos[2 * n + i] : 0.0, zi, zl);
+  } else {
+    xi = ok ? CT(pos[i]) : CT(0);
+    yi = ok ? CT(pos[n + i]) : CT(0);
+    zi = ok ? CT(pos[2 * n + i]) : CT(0);
+  }
   double phi = 0.0;
 
   for (int jt = jbeg; jt < jend; jt += kThreads) {
@@ -341,7 +400,16 @@ __global__ __launch_bounds__(kThreads) void potential_kernel(
 #pragma unroll
         for (int u = 0; u < C; ++u) {
           const Src<PREC> s = tile[(u0 + u) * L + q];
-          const float dx = DT(s.x - xi), dy = DT(s.y - yi), dz = DT(s.z - zi);
+          float dx, dy, dz;
+          if constexpr (PREC == NBODY_MIXED_DS) {
+            dx = ds_diff(s.x, s.xl, xi, xl);
+            dy = ds_diff(s.y, s.yl, yi, yl);
+            dz = ds_diff(s.z, s.zl, zi, zl);
+          } else {
+            dx = DT(s.x - xi);
+            dy = DT(s.y - yi);
+            dz = DT(s.z - zi);
+          }
           float r2 = fmaf(dx, dx, eps2);
           r2 = fmaf(dy, dy, r2);
           r2 = fmaf(dz, dz, r2);
@@ -610,6 +678,9 @@ hipError_t launch_accel(const Plan &pl, int precision, int n, int row0, int nt,
     case NBODY_MIXED_D64:
       return launch_accel_p<NBODY_MIXED_D64>(pl, n, row0, nt, pos, mass, eps2,
                                              scale, out, stride, st);
+    case NBODY_MIXED_DS:
+      return launch_accel_p<NBODY_MIXED_DS>(pl, n, row0, nt, pos, mass, eps2,
+                                            scale, out, stride, st);
   }
   return hipErrorInvalidValue;
 }
@@ -632,6 +703,9 @@ hipError_t launch_vjp(const Plan &pl, int precision, int n, int row0, int nt,
     case NBODY_MIXED_D64:
       return launch_vjp_p<NBODY_MIXED_D64>(pl, n, row0, nt, pos, mass, gacc,
                                            eps2, scale, ox, om, stride, st);
+    case NBODY_MIXED_DS:
+      return launch_vjp_p<NBODY_MIXED_DS>(pl, n, row0, nt, pos, mass, gacc,
+                                          eps2, scale, ox, om, stride, st);
   }
   return hipErrorInvalidValue;
 }
@@ -661,6 +735,7 @@ hipError_t launch_potential(const Plan &pl, int precision, int n,
     case NBODY_MIXED: NBODY_POT(NBODY_MIXED); break;
     case NBODY_MIXED_D64:
     case NBODY_MIXED_NF: NBODY_POT(NBODY_MIXED_D64); break;
+    case NBODY_MIXED_DS: NBODY_POT(NBODY_MIXED_DS); break;
     default: return hipErrorInvalidValue;
   }
 #undef NBODY_POT
@@ -686,6 +761,10 @@ hipError_t launch_diagnostics(int precision, int n, int sj,
     case NBODY_MIXED_D64:
     case NBODY_MIXED_NF:
       diag_block_kernel<NBODY_MIXED_D64><<<nblocks, kThreads, 0, st>>>(
+          n, sj, phi_part, pos, vel, mass, eps2, blocksum);
+      break;
+    case NBODY_MIXED_DS:
+      diag_block_kernel<NBODY_MIXED_DS><<<nblocks, kThreads, 0, st>>>(
           n, sj, phi_part, pos, vel, mass, eps2, blocksum);
       break;
     default:
@@ -730,6 +809,7 @@ hipError_t launch_step_small(int precision, int n, const double *x_in,
     case NBODY_FP64: NBODY_STEP_SMALL(NBODY_FP64); break;
     case NBODY_MIXED: NBODY_STEP_SMALL(NBODY_MIXED); break;
     case NBODY_MIXED_D64: NBODY_STEP_SMALL(NBODY_MIXED_D64); break;
+    case NBODY_MIXED_DS: NBODY_STEP_SMALL(NBODY_MIXED_DS); break;
     default: return hipErrorInvalidValue;
   }
 #undef NBODY_STEP_SMALL

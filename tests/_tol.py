@@ -10,7 +10,12 @@ w_ij = s_ij^-3/2, s_ij = |d_ij|^2 + eps^2 (d_ij = x_j - x_i):
   its far runs, where the workgroup target box's half-diagonal b bounds
   |x_i - c| and every pair has |d_ij| > kappa b = b / 2, so
   delta_ij < 6 u32 |d_ij|, and by u32 |d_ij| on its near runs (the D64
-  arithmetic); FP64 inputs are exact;
+  arithmetic); the two-float difference (NBODY_MIXED_DS),
+  (x_j^hi - x_i^hi) + (x_j^lo - x_i^lo) with hi = fl32(x), lo = fl32(x - hi),
+  by delta_ij <= 2 u32 |d_ij| + 4 u32^2 (|x_i| + |x_j|) (the hi/lo split
+  carries each coordinate to u32^2 |x|, the two FP32 differences and their
+  sum round at most once each at the u32 level of |d| or u32^2 of |x|);
+  FP64 inputs are exact;
 * a perturbation delta of d changes f_ij by at most 4 G m_j w_ij delta
   (|d(d w)/dd| <= w (1 + 3 |d|^2 / s) <= 4 w);
 * the pair arithmetic (three FMAs for s, the hardware reciprocal square root
@@ -41,6 +46,9 @@ VJP_CHUNK32 = 16
 # Far runs of the near / far mode: a pair distance above kappa = 1/2 times
 # the target box's half-diagonal gives delta < (2 + 2 / kappa) u32 |d|.
 NF_DELTA = 6.0
+# Two-float differences: delta <= 2 u32 |d| + 4 u32^2 (|x_i| + |x_j|).
+DS_DELTA = 2.0
+DS_DELTA_X = 4.0
 
 
 def _delta(precision, xn, blk, dn):
@@ -51,6 +59,8 @@ def _delta(precision, xn, blk, dn):
         return U32 * dn
     if precision in ("mixed_nf", "mixed_nf64"):   # nf64: FP64 near runs, within it
         return NF_DELTA * U32 * dn
+    if precision == "mixed_ds":
+        return DS_DELTA * U32 * dn + DS_DELTA_X * U32 * U32 * (xn[blk, None] + xn[None, :])
     if precision == "fp64":
         return 0.0
     raise ValueError(precision)
@@ -130,6 +140,8 @@ def accel_bound(pos, mass, G, eps, precision, rows=None):
             pert = 4.0 * U32 * S1
         elif precision in ("mixed_nf", "mixed_nf64"):
             pert = 4.0 * NF_DELTA * U32 * S1
+        elif precision == "mixed_ds":
+            pert = 4.0 * (DS_DELTA * U32 * S1 + DS_DELTA_X * U32 * U32 * (xi * S0 + S2))
         else:
             raise ValueError(precision)
     return SAFETY * abs(G) * (pert + arith)
@@ -209,6 +221,9 @@ def vjp_bound(pos, mass, gacc, G, eps, precision, rows=None):
     elif precision in ("mixed_nf", "mixed_nf64"):
         px = 12.0 * NF_DELTA * U32 * A[1]
         pm = 4.0 * NF_DELTA * U32 * Be
+    elif precision == "mixed_ds":
+        px = 12.0 * (DS_DELTA * U32 * A[1] + DS_DELTA_X * U32 * U32 * (xk * A[3] + A[2]))
+        pm = 4.0 * (DS_DELTA * U32 * Be + DS_DELTA_X * U32 * U32 * (xk * Bsum + Bx))
     else:
         raise ValueError(precision)
     self_res = u * eps ** -3 * u * mk * gk

@@ -55,6 +55,7 @@ def test_header_enums_match_binding(B):
                       ("NBODY_MIXED_D64", B.NBODY_MIXED_D64),
                       ("NBODY_MIXED_NF", B.NBODY_MIXED_NF),
                       ("NBODY_MIXED_NF64", B.NBODY_MIXED_NF64),
+                      ("NBODY_MIXED_DS", B.NBODY_MIXED_DS),
                       ("NBODY_OP_MORTON_SORT", B.NBODY_OP_MORTON_SORT),
                       ("NBODY_OP_STEP_ADJOINT", B.NBODY_OP_STEP_ADJOINT)]:
         m = re.search(r"\b%s\s*=\s*(\d+)" % name, txt)
@@ -85,7 +86,7 @@ def test_checkpoint_bytes(B):
 
 def test_workspace_bytes(B):
     inv = ctypes.c_size_t(-1).value
-    for prec in (0, 1, 2):
+    for prec in (0, 1, 2, 5):
         for n in (1, 255, 256, 1000, 16384, 65536, 262144):
             step = B.nbody_workspace_bytes(B.NBODY_OP_STEP, n, 10, 1, prec)
             acc = B.nbody_workspace_bytes(B.NBODY_OP_ACCEL, n, 0, 1, prec)
@@ -99,13 +100,13 @@ def test_workspace_bytes(B):
             assert adj >= (3 * 3 + 10 * 3 + 4) * n * 8
             # small systems step in one launch per step, drifting the
             # positions into a second array in the workspace (FP64 up to
-            # n = 2048, D64 up to 1024, mixed up to 512)
-            if n <= {0: 2048, 1: 512, 2: 1024}[prec]:
+            # n = 2048, D64 and DS up to 1024, mixed up to 512)
+            if n <= {0: 2048, 1: 512, 2: 1024, 5: 1024}[prec]:
                 assert step >= acc + 3 * n * 8
         assert B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, 100, 50, 0, prec) == inv
     assert B.nbody_workspace_bytes(7, 100, 0, 1, 0) == inv
     assert B.nbody_workspace_bytes(0, 0, 0, 1, 0) == inv
-    assert B.nbody_workspace_bytes(0, 100, 0, 1, 5) == inv
+    assert B.nbody_workspace_bytes(0, 100, 0, 1, 6) == inv
     assert B.nbody_workspace_bytes(0, B.NBODY_MAX_N + 1, 0, 1, 0) == inv
     # fewer segment positions are needed when steps < ckpt_every
     a = B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, 1000, 3, 10, 0)
@@ -139,7 +140,7 @@ def _accel(B, n=64, pos=FAKE, mass=FAKE, acc=FAKE, prec=0, ws=None, wsb=0, **kw)
     (dict(acc=0), "acc is NULL"), (dict(pos=FAKE + 4), "aligned"),
     (dict(eps=0.0), "eps"), (dict(eps=-1.0), "eps"), (dict(eps=math.nan), "eps"),
     (dict(eps=1e-200), "eps^2"), (dict(G=math.inf), "G is not finite"),
-    (dict(prec=5), "precision"), (dict(prec=-1), "precision"),
+    (dict(prec=6), "precision"), (dict(prec=-1), "precision"),
 ])
 def test_accel_rejects_invalid_arguments(B, kw, msg):
     rc = _accel(B, **kw)
@@ -176,7 +177,8 @@ def test_accel_noalloc_rejects_invalid_arguments(B, kw, msg):
 # first size over it for each precision, and the largest workspaces of the
 # FP32-pair modes (2 source splits of just under 2^21 bodies).
 @pytest.mark.parametrize("n,prec", [(65025, 0), (262144, 0), (932068, 1), (2096891, 1),
-                                    (932068, 2), (681739, 3), (14913073, 4)])
+                                    (932068, 2), (681739, 3), (14913073, 4),
+                                    (932068, 5)])
 def test_accel_noalloc_rejects_sizes_beyond_its_scratch(B, n, prec):
     need = B.nbody_workspace_bytes(B.NBODY_OP_ACCEL, n, 0, 1, prec)
     assert need > B.NBODY_NOALLOC_SCRATCH_BYTES
@@ -191,7 +193,7 @@ def test_accel_noalloc_limits_match_the_header(B):
     txt = open(HEADER).read()
     assert re.search(r"NBODY_NOALLOC_SCRATCH_BYTES \(\(size_t\)64 << 20\)", txt)
     assert lim == 64 << 20
-    first = {0: 65025, 1: 932068, 2: 932068, 3: 681739, 4: 14913073}
+    first = {0: 65025, 1: 932068, 2: 932068, 3: 681739, 4: 14913073, 5: 932068}
     for prec, nf in first.items():
         assert B.nbody_workspace_bytes(B.NBODY_OP_ACCEL, nf, 0, 1, prec) > lim
         grid = sorted(set(list(range(1, min(nf, 70000), 97)) + [nf - 1, nf - 2, nf - 255]
@@ -235,12 +237,12 @@ def test_vjp_and_adjoint_reject_invalid_arguments(B):
     assert adj(steps=-2) == 1
     assert adj(ckpt=0) == 1
     assert adj(gacc=FAKE + 2) == 1
-    assert adj(prec=5) == 1
+    assert adj(prec=6) == 1
     assert adj(flags=1) == 1   # NBODY_ACC_VALID is not an adjoint flag
     assert adj(wsb=ws - 256) == 2
 
 
-@pytest.mark.parametrize("prec", [1, 2, 3, 4])
+@pytest.mark.parametrize("prec", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("eps", [1e-14, 2.0 ** -42 * 0.999, 1e-30, 1e20])
 def test_fp32_pair_modes_reject_eps_outside_fp32_range(B, prec, eps):
     """Every precision but FP64 evaluates the self pair in FP32 with weight
@@ -274,7 +276,7 @@ def test_fp32_pair_modes_accept_the_smallest_eps(B):
     txt = open(HEADER).read()
     assert "#define NBODY_MIN_EPS_FP32 (0x1p-42)" in txt
     # passes the eps check, then fails on the missing workspace
-    for prec in (1, 2, 3, 4):
+    for prec in (1, 2, 3, 4, 5):
         rc = _accel(B, n=65536, prec=prec, eps=2.0 ** -42, ws=None, wsb=0)
         assert rc == 2, lib.nbody_last_error().decode()
 
@@ -292,7 +294,7 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
 def test_rows_workspace_matches_full_call(B):
     # the plan for all n rows is the whole-system plan (same split count, so
     # the same workspace and, on the GPU, bitwise the same result)
-    for prec in (0, 1, 2, 3, 4):
+    for prec in (0, 1, 2, 3, 4, 5):
         for n in (1, 255, 256, 1000, 3001, 16384, 65536, 262144, 1 << 20):
             for op in (B.NBODY_OP_ACCEL, B.NBODY_OP_VJP):
                 assert (B.nbody_rows_workspace_bytes(op, n, n, prec)
@@ -301,7 +303,7 @@ def test_rows_workspace_matches_full_call(B):
 
 def test_rows_workspace_bytes(B):
     inv = ctypes.c_size_t(-1).value
-    for prec in (0, 1, 2, 3, 4):
+    for prec in (0, 1, 2, 3, 4, 5):
         assert B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 1000, 0, prec) == 0
         for n, rows in ((262144, 32768), (262144, 1), (1 << 28, 1), (5000, 77)):
             a = B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, n, rows, prec)
@@ -315,7 +317,7 @@ def test_rows_workspace_bytes(B):
         assert B.nbody_rows_workspace_bytes(B.NBODY_OP_STEP, 1000, 10, prec) == inv
         assert B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 1000, 1001, prec) == inv
         assert B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 1000, -1, prec) == inv
-    assert B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 1000, 10, 5) == inv
+    assert B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, 1000, 10, 6) == inv
 
 
 def test_rows_reject_invalid_ranges(B):
@@ -410,7 +412,7 @@ def test_morton_workspace_bytes(B):
     for n, npad in ((1, 1), (2, 2), (1000, 1024), (1024, 1024), (1025, 2048),
                     (262144, 262144)):
         want = _tile_boxes(n) + 256 + (npad * 8 + 255) // 256 * 256
-        for prec in (0, 1, 2, 3, 4):
+        for prec in (0, 1, 2, 3, 4, 5):
             assert B.nbody_workspace_bytes(B.NBODY_OP_MORTON_SORT, n, 0, 1, prec) == want
 
 

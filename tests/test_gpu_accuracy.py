@@ -9,7 +9,8 @@ regression of the pair arithmetic, the chunk sums or the near / far
 decision fails here.  Rows: all bodies of the N = 16384 cube; for the
 Plummer spheres the seeded rows plus the 256 bodies nearest the centre of
 mass (where the net acceleration nearly cancels and relative errors peak).
-NBODY_MIXED and NBODY_MIXED_D64 run on the bodies in their generated order,
+NBODY_MIXED, NBODY_MIXED_D64 and NBODY_MIXED_DS run on the bodies in their
+generated order,
 the near / far modes on the same bodies in Morton order (sorted by the
 oracle).  The VJP's normwise errors on the same rows are printed.
 """
@@ -40,6 +41,9 @@ CEILING = {
     ("plummer262144_vjp", "mixed_d64"): (7.0e-7, 5.5e-8),
     ("plummer262144_vjp", "mixed_nf"): (1.2e-6, 6.5e-8),
     ("plummer262144_vjp", "mixed_nf64"): (1.0e-6, 5.5e-8),
+    ("cube16384", "mixed_ds"): (3.2e-6, 1.3e-7),
+    ("plummer65536", "mixed_ds"): (1.5e-6, 6.0e-8),
+    ("plummer262144_vjp", "mixed_ds"): (2.3e-6, 6.0e-8),
 }
 
 

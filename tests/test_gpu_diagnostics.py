@@ -19,7 +19,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 U32, U64 = 2.0 ** -24, 2.0 ** -53
-PRECS = ["fp64", "mixed", "mixed_d64", "mixed_nf", "mixed_nf64"]
+PRECS = ["fp64", "mixed", "mixed_d64", "mixed_nf", "mixed_nf64", "mixed_ds"]
 
 
 def say(*a):
@@ -57,6 +57,8 @@ def potential_bound(pos, mass, G, eps, prec):
             delta = U32 * (xn[rows, None] + xn[None, :] + dn)
         elif prec in ("mixed_d64", "mixed_nf"):   # the potential of NF is D64
             delta = U32 * dn
+        elif prec == "mixed_ds":                  # two-float differences
+            delta = 2 * U32 * dn + 4 * U32 * U32 * (xn[rows, None] + xn[None, :])
         else:
             delta = 0.0
         term = mass[None, :] * (c * y + delta / s)

@@ -17,7 +17,7 @@ from paper_2203_08263_amd import inputs, metrics
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp64", "mixed", "mixed_d64", "mixed_nf", "mixed_nf64"]
+PRECS = ["fp64", "mixed", "mixed_d64", "mixed_nf", "mixed_nf64", "mixed_ds"]
 SIZES = [1, 2, 3, 64, 255, 256, 257, 1000, 2049, 5003]
 
 
@@ -224,14 +224,14 @@ def test_step_parity_small(B, dev, oracle, prec):
                  _tol.accel_bound(N(P), mass, 1.0, eps, prec), "final acc")
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed_d64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed_d64", "mixed", "mixed_ds"])
 @pytest.mark.parametrize("n,S", [(100, 1), (100, 2), (100, 3), (512, 4),
                                  (513, 4), (1024, 3), (1025, 3), (2048, 2),
                                  (2049, 2)])
 def test_step_one_launch_loop_sizes(B, dev, oracle, prec, n, S):
     # small systems step in one launch per step (positions alternate between
-    # pos and a workspace copy; FP64 up to n = 2048, D64 up to 1024, mixed up
-    # to 512), larger ones in two: odd and even step counts on both sides of
+    # pos and a workspace copy; FP64 up to n = 2048, D64 and DS up to 1024,
+    # mixed up to 512), larger ones in two: odd and even step counts on both sides of
     # each limit, checked against the oracle with a checkpoint record
     say("step sizes", prec, n, S)
     pos, vel, mass, P, V, M = _state(n, 60 + n + S, dev)
@@ -257,7 +257,7 @@ def test_step_one_launch_loop_sizes(B, dev, oracle, prec, n, S):
         assert metrics.normwise(rec[6:9], as_) <= 1e-12
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed_d64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed_d64", "mixed", "mixed_ds"])
 def test_time_reversibility(B, dev, prec):
     # kick-drift-kick is time-reversible: S steps, velocities negated, S more
     # steps (reusing the cached acceleration) return to the start up to
@@ -422,7 +422,7 @@ def test_adjoint_zero_steps_is_vjp(B, dev, prec):
 
 # ------------------------------------------------------------- autograd ---
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed_d64"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed_d64", "mixed_ds"])
 def test_autograd_accel(B, dev, oracle, prec):
     say("autograd accel", prec)
     from paper_2203_08263_amd import accel

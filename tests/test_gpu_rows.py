@@ -20,7 +20,7 @@ from paper_2203_08263_amd import inputs
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp64", "mixed", "mixed_d64", "mixed_nf", "mixed_nf64"]
+PRECS = ["fp64", "mixed", "mixed_d64", "mixed_nf", "mixed_nf64", "mixed_ds"]
 
 
 def say(*a):

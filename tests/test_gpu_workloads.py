@@ -20,7 +20,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 W = inputs.WORKLOADS
-PRECS = ["fp64", "mixed", "mixed_d64"]
+PRECS = ["fp64", "mixed", "mixed_d64", "mixed_ds"]
 
 
 def say(*a):
@@ -297,7 +297,7 @@ def test_plummer262144_accel_vjp(B, dev, oracle, prec):
 
 # ------------------------------- largest size in the suite: N = 2^20 + 5 --
 
-@pytest.mark.parametrize("prec", ["mixed", "fp64", "mixed_d64", "mixed_nf64"])
+@pytest.mark.parametrize("prec", ["mixed", "fp64", "mixed_d64", "mixed_nf64", "mixed_ds"])
 def test_large_ragged_system_sampled_rows(B, dev, oracle, prec):
     # 1048581 bodies (a ragged last tile; 1.1e12 pairs per call): accel and
     # VJP on 128 seeded rows against the oracle's rows, every row of the

@@ -8,7 +8,7 @@ import pytest
 import _tol
 from paper_2203_08263_amd import inputs
 
-PRECS = ["fp64", "mixed", "mixed_d64", "mixed_nf", "mixed_nf64"]
+PRECS = ["fp64", "mixed", "mixed_d64", "mixed_nf", "mixed_nf64", "mixed_ds"]
 
 
 def _direct_accel(pos, mass, G, eps, prec, rows):

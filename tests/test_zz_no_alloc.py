@@ -22,7 +22,8 @@ pytestmark = pytest.mark.gpu
 # source split; the near / far modes also put their boxes there), the second
 # system ragged and smaller than the first.
 CASES = [("fp64", 40000, 9001), ("mixed", 70001, 20003), ("mixed_d64", 65536, 5001),
-         ("mixed_nf", 131072, 3001), ("mixed_nf64", 90000, 12345)]
+         ("mixed_nf", 131072, 3001), ("mixed_nf64", 90000, 12345),
+         ("mixed_ds", 70001, 4099)]
 
 
 def say(*a):
