@@ -71,7 +71,15 @@ KERNEL_KIND = {"accel": "accel_kernel", "vjp": "vjp_kernel"}
 # 64 MiB device copy), keyed by (kind, precision, N).  Each record names the
 # kernel sources it was taken on (first 16 hex digits of their SHA-256) and
 # is reported as null for any other source.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # profiles/vjp_nf_kernel_plummer262144_counters.md: 203.2 MB fetched +
+    # 67.1 MB written by the second vjp_nf_kernel launch
+    ("vjp", "mixed_nf", 262144): {"bytes": 270267674, "src_sha256": "f46757de62b3fabb"},
+    # same file: 75.5 MB + 50.3 MB, accel_nf_kernel
+    ("accel", "mixed_nf", 262144): {"bytes": 125810681, "src_sha256": "f46757de62b3fabb"},
+    # profiles/accel_kernel_plummer65536_mixed.md: 16.8 MB + 50.3 MB
+    ("accel", "mixed", 65536): {"bytes": 67167428, "src_sha256": "f46757de62b3fabb"},
+}
 KERNEL_SRC = [os.path.join(ROOT, "paper_2203_08263_amd", "csrc", f)
               for f in ("nbody_kernels.hip", "nbody_nearfar.hip", "nbody_device.h")]
 

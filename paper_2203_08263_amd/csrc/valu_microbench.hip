@@ -2,7 +2,10 @@
 // all-pairs kernels are made of: FP32/FP64 fused multiply-add, multiply and
 // add, the hardware reciprocal square root (v_rsq_f32 / v_rsq_f64), FP64 ->
 // FP32 conversion, and an FMA stream with one reciprocal square root per 12
-// FMAs (the mixed forward pair's mix).
+// FMAs (the mixed forward pair's mix).  It also times a grid-wide barrier
+// (cooperative-groups grid sync in a kernel launched cooperatively) for
+// several grid sizes: the cost a one-launch multi-step loop would pay per
+// step.
 //
 // Every thread runs kChains independent dependency chains for `iters`
 // iterations and writes one value, so the loop cannot be removed; the grid
@@ -12,6 +15,7 @@
 // the two hardware reciprocal square root estimates (largest relative error
 // over 4M arguments spread over many binades), which sets how much
 // refinement the FP64 kernels need.  Output: one JSON object per line.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -154,6 +158,20 @@ __global__ __launch_bounds__(kThreads) void cvt_chain(int iters, double seed,
   out[blockIdx.x * kThreads + threadIdx.x] = s;
 }
 
+// `iters` grid-wide barriers (every workgroup runs the same count, so all
+// of them reach every barrier); launched only through
+// hipLaunchCooperativeKernel, which refuses a grid that cannot be resident.
+__global__ __launch_bounds__(kThreads) void grid_syncs(int iters,
+                                                       double *__restrict__ out) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  double acc = threadIdx.x;
+  for (int it = 0; it < iters; ++it) {
+    acc = acc * 1.0000001 + 1.0;
+    grid.sync();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = acc;
+}
+
 // Relative error |1 - s y^2| / 2 of the hardware estimate y of s^(-1/2):
 // FP64 arguments in [2^-60, 2^60), FP32 ones in [2^-20, 2^20), mantissas
 // from a counter-based hash of the sample index.
@@ -289,6 +307,27 @@ int main(int argc, char **argv) {
   CHECK(hipFree(stamp));
   report("cvt_f32_f64+cvt_f64_f32+mul_f64 (per op)",
          time_ms([&] { cvt_chain<<<blocks, kThreads, 0, st>>>(iters, 1.0, d); }, st), 3);
+
+  // Grid-wide barrier cost: 1000 barriers per launch, several grid sizes up
+  // to what can be resident (the occupancy query bounds the grid).
+  int coop = 0, per_cu = 0;
+  CHECK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, grid_syncs,
+                                                     kThreads, 0));
+  if (coop) {
+    for (int gb : {8, 64, 256, 1024}) {
+      if (gb > per_cu * cus || size_t(gb) > nthreads) continue;
+      int nsync = 1000;
+      void *args[] = {&nsync, &d};
+      const double ms = time_ms([&] {
+        CHECK(hipLaunchCooperativeKernel((void *)grid_syncs, dim3(gb),
+                                         dim3(kThreads), args, 0, st));
+      }, st);
+      printf("{\"op\": \"cooperative grid sync\", \"workgroups\": %d, "
+             "\"ms\": %.4f, \"us_per_sync\": %.3f}\n", gb, ms, ms * 1e3 / nsync);
+      fflush(stdout);
+    }
+  }
 
   const int nacc = 1 << 22;
   double *err = nullptr;
