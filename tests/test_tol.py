@@ -77,3 +77,80 @@ def test_sums_cache_keys_on_content():
     assert not np.array_equal(b1, b2)
     np.testing.assert_array_equal(_tol.accel_bound(pos, mass, 1.0, 1e-3, "mixed", rows),
                                   b1)
+
+
+# ------------------------------------------------------------------------
+# The per-pair coordinate perturbations that every bound above is built on,
+# checked against the FP32 arithmetic itself (NumPy float32 operations round
+# correctly, as the GPU's do): random pairs over many decades of separation
+# and offset, componentwise exactly as the kernels form the difference.
+
+def _pairs(seed, m=200000):
+    rng = np.random.default_rng(seed)
+    off = 10.0 ** rng.uniform(-3, 3, m) * rng.choice([-1, 1], m)
+    xi = off[None, :] + rng.normal(size=(3, m)) * 10.0 ** rng.uniform(-3, 1, m)
+    d = rng.normal(size=(3, m)) * 10.0 ** rng.uniform(-7, 0.5, m)
+    xj = xi + d
+    d = xj - xi                       # the FP64 difference the oracle sees
+    return xi, xj, d
+
+
+def _worst(err, bound):
+    return float(np.max(np.linalg.norm(err, axis=0) / bound))
+
+
+def test_mixed_difference_within_delta():
+    xi, xj, d = _pairs(1)
+    got = (xj.astype(np.float32) - xi.astype(np.float32)).astype(np.float64)
+    xn = np.stack([np.linalg.norm(xi, axis=0), np.linalg.norm(xj, axis=0)])
+    bound = _tol.U32 * (xn[0] + xn[1] + np.linalg.norm(d, axis=0))
+    assert _worst(got - d, bound) <= 1.0
+
+
+def test_d64_difference_within_delta():
+    xi, xj, d = _pairs(2)
+    got = (xj - xi).astype(np.float32).astype(np.float64)
+    bound = _tol.U32 * np.linalg.norm(d, axis=0) * (1 + 2 * _tol.U64 / _tol.U32)
+    assert _worst(got - d, bound) <= 1.0
+
+
+def test_two_float_difference_within_delta():
+    """NBODY_MIXED_DS: hi = fl32(x), lo = fl32(x - hi); the difference is
+    (x_j^hi - x_i^hi) + (x_j^lo - x_i^lo) in FP32."""
+    xi, xj, d = _pairs(3)
+
+    def split(x):
+        hi = x.astype(np.float32)
+        lo = (x - hi.astype(np.float64)).astype(np.float32)
+        return hi, lo
+    ih, il = split(xi)
+    jh, jl = split(xj)
+    got = ((jh - ih) + (jl - il)).astype(np.float64)          # float32 operations
+    xn = np.linalg.norm(xi, axis=0) + np.linalg.norm(xj, axis=0)
+    bound = (_tol.DS_DELTA * _tol.U32 * np.linalg.norm(d, axis=0)
+             + _tol.DS_DELTA_X * _tol.U32 ** 2 * xn)
+    w = _worst(got - d, bound)
+    assert w <= 1.0
+    # and it is not loose by orders of magnitude: the worst pair uses a good
+    # part of it
+    assert w >= 0.1
+
+
+def test_near_far_recentred_difference_within_delta():
+    """Far runs of the near / far modes: x - c rounded once to FP32 for both
+    bodies (c the target box's centre, |x_i - c| <= b), pairs with
+    |d| > kappa b (kappa = 1/2): delta < 6 u32 |d|."""
+    rng = np.random.default_rng(4)
+    m = 200000
+    b = 10.0 ** rng.uniform(-4, 1, m)
+    c = rng.normal(size=(3, m)) * 10.0 ** rng.uniform(-2, 3, m)
+    u = rng.normal(size=(3, m))
+    u /= np.linalg.norm(u, axis=0)
+    xi = c + u * b * rng.uniform(0, 1, m)                      # |x_i - c| <= b
+    dirn = rng.normal(size=(3, m))
+    dirn /= np.linalg.norm(dirn, axis=0)
+    xj = xi + dirn * b * (0.5 + 10.0 ** rng.uniform(-6, 3, m))  # |d| > b / 2
+    d = xj - xi
+    got = ((xj - c).astype(np.float32) - (xi - c).astype(np.float32)).astype(np.float64)
+    bound = _tol.NF_DELTA * _tol.U32 * np.linalg.norm(d, axis=0)
+    assert _worst(got - d, bound) <= 1.0
