@@ -463,7 +463,10 @@ class Rollout16384:
 def adjoint_leg(torch, B, inputs):
     """The forward + adjoint configuration: N = 8192 uniform cube, 50 KDK
     steps with a checkpoint every 10, then the reverse sweep (which
-    recomputes each segment).  Step-level t_bwd / t_fwd per precision."""
+    recomputes each segment).  Step-level t_bwd / t_fwd per precision; and,
+    as `mixed_auto_K`, the same with the interval rollout(ckpt_every="auto")
+    picks for a 1 GiB budget (every state stored: no recomputation)."""
+    from paper_2203_08263_amd import auto_ckpt_every
     dev = torch.device("cuda:0")
     w = inputs.WORKLOADS["cube8192_adjoint"]
     T = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa
@@ -472,12 +475,12 @@ def adjoint_leg(torch, B, inputs):
     GX0 = T(inputs.upstream_normal(w.n, w.seed + 500))
     P, V, A = torch.empty_like(P0), torch.empty_like(P0), torch.empty_like(P0)
     GX, GV, GM = torch.empty_like(P0), torch.empty_like(P0), torch.empty_like(M)
-    K = w.ckpt_every
-    CK = torch.empty(B.nbody_checkpoint_bytes(w.n, w.steps, K) // 8, dtype=torch.float64,
-                     device=dev)
     out = {"workload": "cube8192_adjoint: N=%d, %d KDK steps, checkpoint every %d"
-                       % (w.n, w.steps, K)}
-    for p in ("mixed", "fp64"):
+                       % (w.n, w.steps, w.ckpt_every)}
+    for p, K, key in (("mixed", w.ckpt_every, "mixed"), ("fp64", w.ckpt_every, "fp64"),
+                      ("mixed", auto_ckpt_every(w.n, w.steps, "mixed"), "mixed_auto_K")):
+        CK = torch.empty(B.nbody_checkpoint_bytes(w.n, w.steps, K) // 8,
+                         dtype=torch.float64, device=dev)
         ws = torch.empty(max(B.nbody_workspace_bytes(B.NBODY_OP_STEP, w.n, w.steps, K, p),
                              B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, w.n,
                                                      w.steps, K, p)),
@@ -498,10 +501,10 @@ def adjoint_leg(torch, B, inputs):
         tf = event_ms(torch, fwd, 3)
         fwd()   # the adjoint reads this forward's checkpoints
         tb = event_ms(torch, bwd, 3, warmup=0)
-        out[p] = {"fwd_ms": round(tf, 4), "bwd_ms": round(tb, 4),
-                  "bwd_over_fwd": round(tb / tf, 3),
-                  "fwd_adj_G_int_s": round(float(w.n) * w.n * w.steps / ((tf + tb) * 1e-3)
-                                           / 1e9, 1)}
+        out[key] = {"ckpt_every": K, "fwd_ms": round(tf, 4), "bwd_ms": round(tb, 4),
+                    "bwd_over_fwd": round(tb / tf, 3),
+                    "fwd_adj_G_int_s": round(float(w.n) * w.n * w.steps
+                                             / ((tf + tb) * 1e-3) / 1e9, 1)}
     return out
 
 

@@ -13,16 +13,17 @@ import importlib
 
 _BINDING = (
     "NBODY_FP64", "NBODY_MIXED", "NBODY_MIXED_D64", "NBODY_MIXED_NF",
-    "NBODY_MIXED_NF64", "PRECISIONS",
+    "NBODY_MIXED_NF64", "NBODY_MIXED_DS", "PRECISIONS",
     "NBodyError", "nbody_morton_sort", "nbody_accel_f32", "nbody_step_f32",
     "nbody_f32_workspace_bytes",
-    "nbody_accel", "nbody_accel_vjp", "nbody_step", "nbody_step_adjoint",
+    "nbody_accel", "nbody_accel_noalloc", "nbody_accel_vjp", "nbody_step",
+    "nbody_step_adjoint",
     "nbody_diagnostics", "nbody_accel_rows", "nbody_accel_vjp_rows",
     "nbody_workspace_bytes", "nbody_rows_workspace_bytes",
     "nbody_checkpoint_bytes", "library_path",
     "load_library",
 )
-_AUTOGRAD = ("NBodyAccel", "NBodyRollout", "accel", "rollout")
+_AUTOGRAD = ("NBodyAccel", "NBodyRollout", "accel", "rollout", "auto_ckpt_every")
 
 __all__ = list(_BINDING + _AUTOGRAD)
 

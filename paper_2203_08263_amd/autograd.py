@@ -78,7 +78,31 @@ def accel(pos, mass, G=1.0, eps=1e-3, precision="fp64"):
     return NBodyAccel.apply(pos, mass, G, eps, B._precision(precision))
 
 
+def auto_ckpt_every(n, steps, precision="fp64", budget_bytes=1 << 30):
+    """The smallest checkpoint interval K whose checkpoint buffer plus the
+    adjoint's workspace (which holds K segment positions) fits in
+    budget_bytes; K = 1 stores every state and needs no recomputation in the
+    reverse sweep (one VJP per step), larger K recompute K - 1 forward
+    evaluations per K steps.  Sizes come from the library."""
+    steps = int(steps)
+    prec = B._precision(precision)
+    best = None
+    for K in range(1, max(1, steps) + 1):
+        need = (B.nbody_checkpoint_bytes(n, steps, K)
+                + B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, n, steps, K, prec))
+        if need <= budget_bytes:
+            return K
+        if best is None or need < best[0]:
+            best = (need, K)
+    return best[1]
+
+
 def rollout(pos0, vel0, mass, G=1.0, eps=1e-3, dt=1e-3, steps=1, ckpt_every=10,
-            precision="fp64", integrator="kdk"):
+            precision="fp64", integrator="kdk", memory_budget=1 << 30):
+    """(x_S, v_S, a_S) with a checkpointed adjoint.  ckpt_every="auto" picks
+    the smallest interval whose checkpoints and adjoint workspace fit in
+    memory_budget bytes (auto_ckpt_every)."""
+    if ckpt_every == "auto":
+        ckpt_every = auto_ckpt_every(mass.shape[0], steps, precision, memory_budget)
     return NBodyRollout.apply(pos0, vel0, mass, G, eps, dt, steps, ckpt_every,
                               B._precision(precision), integrator)

@@ -281,6 +281,26 @@ def test_fp32_pair_modes_accept_the_smallest_eps(B):
         assert rc == 2, lib.nbody_last_error().decode()
 
 
+def test_auto_checkpoint_interval_fits_the_budget(B):
+    from paper_2203_08263_amd import auto_ckpt_every
+    assert auto_ckpt_every(8192, 50) == 1               # every state fits in 1 GiB
+    for n, S, budget in ((8192, 50, 10 << 20), (262144, 1000, 1 << 30),
+                         (1 << 20, 200, 4 << 30), (200, 12, 120000)):
+        K = auto_ckpt_every(n, S, "mixed", budget)
+        need = (B.nbody_checkpoint_bytes(n, S, K)
+                + B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, n, S, K, 1))
+        assert 1 <= K <= S and need <= budget, (n, S, K, need)
+        if K > 1:                                       # and it is the smallest
+            prev = (B.nbody_checkpoint_bytes(n, S, K - 1)
+                    + B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, n, S, K - 1, 1))
+            assert prev > budget
+    # nothing fits: the interval with the smallest footprint
+    need = {K: B.nbody_checkpoint_bytes(200, 12, K)
+            + B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, 200, 12, K, 1)
+            for K in range(1, 13)}
+    assert auto_ckpt_every(200, 12, "mixed", 20000) == min(need, key=need.get)
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     from paper_2203_08263_amd import binding
     monkeypatch.setattr(binding, "_lib", None)

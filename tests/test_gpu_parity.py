@@ -471,6 +471,35 @@ def test_autograd_rollout(B, dev, oracle, prec):
         assert np.all(np.abs(N(M.grad) - rm) <= bm + 1e-6 * np.abs(rm).max())
 
 
+@pytest.mark.parametrize("budget,want_K", [(1 << 30, 1), (120000, None)])
+def test_autograd_rollout_auto_checkpoint_interval(B, dev, budget, want_K):
+    # ckpt_every="auto" picks the smallest interval that fits the memory
+    # budget; the gradients are bitwise those of that interval given
+    # explicitly (and, by K-invariance of the sweep, of every other one)
+    say("autograd rollout auto K", budget)
+    from paper_2203_08263_amd import auto_ckpt_every, rollout
+    n, S = 200, 12
+    K = auto_ckpt_every(n, S, "mixed", budget)
+    if want_K is not None:
+        assert K == want_K
+    else:
+        assert 1 < K <= S
+    pos, vel, mass = inputs.uniform_cube(n, 61)
+    grads = []
+    for k in ("auto", K, 5):
+        P = T(pos, dev).requires_grad_(True)
+        V = T(vel, dev).requires_grad_(True)
+        M = T(mass, dev).requires_grad_(True)
+        xS, vS, _ = rollout(P, V, M, 1.0, 1e-3, 1e-3, S, k, "mixed",
+                            memory_budget=budget)
+        ((xS ** 2).sum() + (vS ** 2).sum()).backward()
+        grads.append([N(t.grad) for t in (P, V, M)])
+    for a, b in zip(grads[0], grads[1]):
+        assert np.array_equal(a, b)
+    for a, b in zip(grads[0], grads[2]):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("integrator", ["kdk", "half_kick_drift"])
 def test_autograd_gradcheck_fp64(B, dev, integrator):
     # torch's own finite-difference Jacobian check of both wrappers on a tiny
