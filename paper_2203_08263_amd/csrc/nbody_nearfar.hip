@@ -193,6 +193,23 @@ __device__ __forceinline__ uint64_t far_runs(const Box &wave, double thr2,
   return __ballot(far);
 }
 
+// far_runs' result when every run of a tile is far for the wave.
+template <int RUN>
+constexpr uint64_t all_runs_mask() {
+  constexpr int NR = kThreads / RUN;
+  return NR >= 64 ? ~uint64_t(0) : ((uint64_t(1) << NR) - 1);
+}
+
+// Whether any wave of the workgroup has a near run in the current tile (the
+// flags each wave's first lane wrote before the barrier): only then is the
+// near form of the tile staged.
+__device__ __forceinline__ bool any_wave_near(const int *wave_near) {
+  int any = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) any |= wave_near[w];
+  return any != 0;
+}
+
 // Centre and far threshold (kappa b)^2 of the workgroup's target box.
 __device__ __forceinline__ double far_frame(const Box &block, double c[3]) {
   double b2 = 0.0;
@@ -246,6 +263,7 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
   using NearSrc = Src<NEAR64 ? NBODY_FP64 : NBODY_MIXED_D64>;
   __shared__ NearSrc near_tile[kThreads];
   __shared__ Src<NBODY_MIXED> far_tile[kThreads];
+  __shared__ int wave_near[kThreads / 64];
 
   const int tid = threadIdx.x;
   const int g = tid / L, q = tid % L;
@@ -288,11 +306,37 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
       bf.m = mj;
     }
     const uint64_t far_mask = far_runs<RUN>(wave, thr2, bx.run, jt, jend);
-    __syncthreads();  // previous tile fully consumed
-    near_tile[tid] = bn;
+    // the all-far path (measured: -2 % at N = 262144 for NBODY_MIXED_NF at
+    // L = 1, -3 % for NBODY_MIXED_NF64) except NBODY_MIXED_NF at L > 1, where
+    // its second copy of the pair loop would cost occupancy (66 VGPRs)
+    constexpr bool kFast = NEAR64 || L == 1;
+    const bool all_far = kFast && far_mask == all_runs_mask<RUN>();
+    if (kFast && (tid & 63) == 0) wave_near[tid / 64] = !all_far;
+    __syncthreads();  // previous tile fully consumed; the waves' flags visible
+    if (!kFast || any_wave_near(wave_near)) near_tile[tid] = bn;
     far_tile[tid] = bf;
     __syncthreads();
 
+    if constexpr (kFast) if (all_far) {
+      // every run of this tile is far for the wave: no per-chunk decisions
+#pragma unroll 2
+      for (int u0 = 0; u0 < PER; u0 += C) {
+        float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+        chunk_sum_f32<C, kNfFarBatch>(
+            [&](int u, float &dx, float &dy, float &dz, float &m) {
+              const Src<NBODY_MIXED> s = far_tile[(u0 + u) * L + q];
+              dx = s.x - xr;
+              dy = s.y - yr;
+              dz = s.z - zr;
+              m = s.m;
+            },
+            eps2, fx, fy, fz);
+        ax += double(fx);
+        ay += double(fy);
+        az += double(fz);
+      }
+      continue;
+    }
     for (int u0 = 0; u0 < PER; u0 += C) {
       const bool far = (far_mask >> (u0 / C)) & 1u;  // run u0 / C of the tile
       if (NEAR64 && !far) {
@@ -356,6 +400,7 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
   using NearSrc = VSrc<NEAR64 ? NBODY_FP64 : NBODY_MIXED_D64>;
   __shared__ NearSrc near_tile[kThreads];
   __shared__ VSrc<NBODY_MIXED> far_tile[kThreads];
+  __shared__ int wave_near[kThreads / 64];
 
   const int tid = threadIdx.x;
   const int g = tid / L, q = tid % L;
@@ -425,11 +470,33 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
     bf.gy = gjy;
     bf.gz = gjz;
     const uint64_t far_mask = far_runs<RUN>(wave, thr2, bx.run, jt, jend);
-    __syncthreads();
-    near_tile[tid] = bn;
+    // NBODY_MIXED_NF64 only (measured: -3 % time there; for NBODY_MIXED_NF
+    // the second copy of the pair loop costs occupancy, 64 -> 67 VGPRs, and
+    // gains nothing)
+    const bool all_far = NEAR64 && far_mask == all_runs_mask<RUN>();
+    if (NEAR64 && (tid & 63) == 0) wave_near[tid / 64] = !all_far;
+    __syncthreads();  // previous tile fully consumed; the waves' flags visible
+    if (!NEAR64 || any_wave_near(wave_near)) near_tile[tid] = bn;
     far_tile[tid] = bf;
     __syncthreads();
 
+    if constexpr (NEAR64) if (all_far) {
+      // every run of this tile is far for the wave: no per-chunk decisions
+      for (int u0 = 0; u0 < PER; u0 += C) {
+        float fx = 0.0f, fy = 0.0f, fz = 0.0f, fm = 0.0f;
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+          const VSrc<NBODY_MIXED> s = far_tile[(u0 + u) * L + q];
+          vjp_pair<float>(s.x - xr, s.y - yr, s.z - zr, s.m, s.gx, s.gy, s.gz,
+                          mk, gkx, gky, gkz, eps2, fx, fy, fz, fm);
+        }
+        sx += double(fx);
+        sy += double(fy);
+        sz += double(fz);
+        sm += double(fm);
+      }
+      continue;
+    }
     for (int u0 = 0; u0 < PER; u0 += C) {
       const bool far = (far_mask >> (u0 / C)) & 1u;
       if (NEAR64 && !far) {
