@@ -1,6 +1,8 @@
 // gfx950 kernels of the near / far precision modes (NBODY_MIXED_NF and
 // NBODY_MIXED_NF64) and of the Morton (Z-order) sort that puts bodies in the
 // spatial order those modes are fast in.
+#include <type_traits>
+
 #include "nbody_device.h"
 
 namespace nbody {
@@ -65,6 +67,12 @@ constexpr int nf_run(KernelKind kind, int L, bool near64) {
 
 struct Box {
   double lo[3], hi[3];
+};
+
+// Near form of a source for NBODY_MIXED_NF: its FP64 coordinates only (the
+// D64 arithmetic takes the mass and dL/da in FP32, from the far tile).
+struct NearXYZ {
+  double x, y, z;
 };
 
 // Minimum over the lanes of each aligned group of `width` lanes (a power of
@@ -260,7 +268,7 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
   constexpr int PER = kThreads / L;
   constexpr int C = nf_run(kAccel, L, NEAR64) / L;  // sources per lane and run
   constexpr int RUN = C * L;  // sources of one chunk run (box granularity)
-  using NearSrc = Src<NEAR64 ? NBODY_FP64 : NBODY_MIXED_D64>;
+  using NearSrc = std::conditional_t<NEAR64, Src<NBODY_FP64>, NearXYZ>;
   __shared__ NearSrc near_tile[kThreads];
   __shared__ Src<NBODY_MIXED> far_tile[kThreads];
   __shared__ int wave_near[kThreads / 64];
@@ -297,7 +305,7 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
     bn.x = xj;
     bn.y = yj;
     bn.z = zj;
-    if constexpr (NEAR64) bn.m = mj64; else bn.m = mj;
+    if constexpr (NEAR64) bn.m = mj64;
     Src<NBODY_MIXED> bf{};
     if (valid) {
       bf.x = float(xj - c[0]);
@@ -339,13 +347,16 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
     }
     for (int u0 = 0; u0 < PER; u0 += C) {
       const bool far = (far_mask >> (u0 / C)) & 1u;  // run u0 / C of the tile
-      if (NEAR64 && !far) {
+      if constexpr (NEAR64) {
+        if (!far) {
 #pragma unroll 4
-        for (int u = 0; u < C; ++u) {
-          const NearSrc s = near_tile[(u0 + u) * L + q];
-          pair_f64(s.x - xi, s.y - yi, s.z - zi, double(s.m), eps2d, ax, ay, az);
+          for (int u = 0; u < C; ++u) {
+            const NearSrc s = near_tile[(u0 + u) * L + q];
+            pair_f64(s.x - xi, s.y - yi, s.z - zi, double(s.m), eps2d, ax, ay,
+                     az);
+          }
+          continue;
         }
-        continue;
       }
       float fx = 0.0f, fy = 0.0f, fz = 0.0f;
       if (far) {
@@ -365,7 +376,7 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
               dx = float(s.x - xi);
               dy = float(s.y - yi);
               dz = float(s.z - zi);
-              m = float(s.m);
+              m = far_tile[(u0 + u) * L + q].m;
             },
             eps2, fx, fy, fz);
       }
@@ -397,7 +408,7 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
   constexpr int PER = kThreads / L;
   constexpr int C = nf_run(kVjp, L, NEAR64) / L;
   constexpr int RUN = C * L;
-  using NearSrc = VSrc<NEAR64 ? NBODY_FP64 : NBODY_MIXED_D64>;
+  using NearSrc = std::conditional_t<NEAR64, VSrc<NBODY_FP64>, NearXYZ>;
   __shared__ NearSrc near_tile[kThreads];
   __shared__ VSrc<NBODY_MIXED> far_tile[kThreads];
   __shared__ int wave_near[kThreads / 64];
@@ -453,11 +464,6 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
       bn.gx = gjx64;
       bn.gy = gjy64;
       bn.gz = gjz64;
-    } else {
-      bn.m = mj;
-      bn.gx = gjx;
-      bn.gy = gjy;
-      bn.gz = gjz;
     }
     VSrc<NBODY_MIXED> bf{};
     if (valid) {
@@ -499,15 +505,17 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
     }
     for (int u0 = 0; u0 < PER; u0 += C) {
       const bool far = (far_mask >> (u0 / C)) & 1u;
-      if (NEAR64 && !far) {
+      if constexpr (NEAR64) {
+        if (!far) {
 #pragma unroll 2
-        for (int u = 0; u < C; ++u) {
-          const NearSrc s = near_tile[(u0 + u) * L + q];
-          vjp_pair<double>(s.x - xk, s.y - yk, s.z - zk, double(s.m),
-                           double(s.gx), double(s.gy), double(s.gz), mk64, gkx64,
-                           gky64, gkz64, eps2d, sx, sy, sz, sm);
+          for (int u = 0; u < C; ++u) {
+            const NearSrc s = near_tile[(u0 + u) * L + q];
+            vjp_pair<double>(s.x - xk, s.y - yk, s.z - zk, double(s.m),
+                             double(s.gx), double(s.gy), double(s.gz), mk64,
+                             gkx64, gky64, gkz64, eps2d, sx, sy, sz, sm);
+          }
+          continue;
         }
-        continue;
       }
       float fx = 0.0f, fy = 0.0f, fz = 0.0f, fm = 0.0f;
       if (far) {
@@ -521,9 +529,10 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
 #pragma unroll
         for (int u = 0; u < C; ++u) {
           const NearSrc s = near_tile[(u0 + u) * L + q];
+          const VSrc<NBODY_MIXED> f = far_tile[(u0 + u) * L + q];
           vjp_pair<float>(float(s.x - xk), float(s.y - yk), float(s.z - zk),
-                          float(s.m), float(s.gx), float(s.gy), float(s.gz), mk,
-                          gkx, gky, gkz, eps2, fx, fy, fz, fm);
+                          f.m, f.gx, f.gy, f.gz, mk, gkx, gky, gkz, eps2, fx,
+                          fy, fz, fm);
         }
       }
       sx += double(fx);
