@@ -152,6 +152,15 @@ enum nbody_op {
  * the library cannot check on the host (masses live in device memory). */
 #define NBODY_MIN_EPS_FP32 (0x1p-42)
 
+/* Smallest softening length the VJP calls (nbody_accel_vjp,
+ * nbody_accel_vjp_rows, nbody_step_adjoint) accept in every precision other
+ * than NBODY_FP64 (2^-32).  Their FP32 pair keeps the weight
+ * s^(-5/2) (e.h) of the e term apart from e, and over all pair distances
+ * that weight reaches 0.29 eps^-4 H with H = m_k |gbar_j| + m_j |gbar_k|:
+ * 2^-32 keeps it finite for H up to about 3.5 (the data-dependent part, H,
+ * is again the caller's to keep in range). */
+#define NBODY_MIN_EPS_FP32_VJP (0x1p-32)
+
 /* Largest supported body count. */
 #define NBODY_MAX_N ((int64_t)1 << 28)
 
@@ -249,7 +258,8 @@ int nbody_step(int64_t n, int64_t steps, double *pos, double *vel,
  *  gpos [vector] out   dL/dx (overwritten, not accumulated)
  *  gmass[scalar] out   dL/dm (overwritten)
  *  ws            >= nbody_workspace_bytes(NBODY_OP_VJP)
- * Errors: as nbody_accel. */
+ * Errors: as nbody_accel, with NBODY_MIN_EPS_FP32_VJP in place of
+ * NBODY_MIN_EPS_FP32. */
 int nbody_accel_vjp(int64_t n, const double *pos, const double *mass,
                     const double *gacc, double *gpos, double *gmass,
                     const nbody_params *p, int precision, void *ws,
@@ -276,7 +286,8 @@ int nbody_accel_vjp(int64_t n, const double *pos, const double *mass,
  *  flags          0 or NBODY_HALF_KICK_DRIFT (as given to nbody_step)
  * steps == 0 gives gpos += VJP_x(x_0; gacc_T), gmass = VJP_m(x_0; gacc_T)
  * (gvel unchanged), reading x_0 from checkpoint record 0.
- * Errors: as nbody_step; ckpt_every must be >= 1. */
+ * Errors: as nbody_step, with NBODY_MIN_EPS_FP32_VJP in place of
+ * NBODY_MIN_EPS_FP32; ckpt_every must be >= 1. */
 int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
                        const double *ckpt, const double *mass,
                        const nbody_params *p, int precision, unsigned flags,
@@ -332,7 +343,8 @@ int nbody_accel_rows(int64_t n, int64_t row_begin, int64_t row_count,
  *  pos, mass [all n] in;  gacc [vector] in  dL/da of all n bodies
  *  gpos [row vector] out;  gmass [row scalar] out
  *  ws   >= nbody_rows_workspace_bytes(NBODY_OP_VJP, n, row_count, precision)
- * Errors: as nbody_accel_rows. */
+ * Errors: as nbody_accel_rows, with NBODY_MIN_EPS_FP32_VJP in place of
+ * NBODY_MIN_EPS_FP32. */
 int nbody_accel_vjp_rows(int64_t n, int64_t row_begin, int64_t row_count,
                          const double *pos, const double *mass,
                          const double *gacc, double *gpos, double *gmass,

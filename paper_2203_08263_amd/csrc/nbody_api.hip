@@ -145,7 +145,7 @@ bool valid_precision(int p) {
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 int check_common(int64_t n, const nbody_params *p, int precision,
-                 bool need_dt) {
+                 bool need_dt, bool vjp = false) {
   if (n < 1 || n > NBODY_MAX_N)
     return fail(NBODY_ERR_INVALID_ARGUMENT, "n = %lld outside [1, %lld]",
                 (long long)n, (long long)NBODY_MAX_N);
@@ -164,14 +164,17 @@ int check_common(int64_t n, const nbody_params *p, int precision,
   // Every precision but NBODY_FP64 evaluates pairs in FP32, the self pair
   // (d = 0) included: its weight m eps^-3 multiplies d = 0, which gives 0 only
   // while eps^2 is a normal FP32 number (not flushed to 0) and eps^-3 is
-  // finite in FP32; otherwise every output would be NaN.
+  // finite in FP32; otherwise every output would be NaN.  The FP32 VJP pair
+  // also forms s^-5/2 (e.h) before multiplying by e, which reaches
+  // 0.29 eps^-4 (m_k |gbar_j| + m_j |gbar_k|): a larger smallest eps there.
   if (precision != NBODY_FP64) {
     const float e2 = float(p->eps * p->eps);
-    if (!(p->eps >= NBODY_MIN_EPS_FP32) || !isfinite(e2))
+    const double min_eps = vjp ? NBODY_MIN_EPS_FP32_VJP : NBODY_MIN_EPS_FP32;
+    if (!(p->eps >= min_eps) || !isfinite(e2))
       return fail(NBODY_ERR_INVALID_ARGUMENT,
                   "eps = %g outside the FP32 pair range [%g, 1.8e19] of "
-                  "precision %d",
-                  p->eps, NBODY_MIN_EPS_FP32, precision);
+                  "precision %d%s",
+                  p->eps, min_eps, precision, vjp ? " (VJP)" : "");
   }
   return NBODY_OK;
 }
@@ -552,7 +555,7 @@ int nbody_accel_vjp_rows(int64_t n, int64_t row_begin, int64_t row_count,
                          const nbody_params *p, int precision, void *ws,
                          size_t ws_bytes, void *stream) {
   int rc;
-  if ((rc = check_common(n, p, precision, false))) return rc;
+  if ((rc = check_common(n, p, precision, false, true))) return rc;
   precision = nbody::effective_precision(precision, n);
   if ((rc = check_rows(n, row_begin, row_count))) return rc;
   if (row_count == 0) return NBODY_OK;
@@ -678,7 +681,7 @@ int nbody_accel_vjp(int64_t n, const double *pos, const double *mass,
                     const nbody_params *p, int precision, void *ws,
                     size_t ws_bytes, void *stream) {
   int rc;
-  if ((rc = check_common(n, p, precision, false))) return rc;
+  if ((rc = check_common(n, p, precision, false, true))) return rc;
   precision = nbody::effective_precision(precision, n);
   if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(mass, "mass")) ||
       (rc = check_ptr(gacc, "gacc")) || (rc = check_ptr(gpos, "gpos")) ||
@@ -711,7 +714,7 @@ int nbody_step_adjoint(int64_t n, int64_t steps, int64_t ckpt_every,
                        double *gpos, double *gvel, const double *gacc_T,
                        double *gmass, void *ws, size_t ws_bytes, void *stream) {
   int rc;
-  if ((rc = check_common(n, p, precision, true))) return rc;
+  if ((rc = check_common(n, p, precision, true, true))) return rc;
   precision = nbody::effective_precision(precision, n);
   if (flags & ~NBODY_HALF_KICK_DRIFT)
     return fail(NBODY_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x",

@@ -147,6 +147,69 @@ __device__ __forceinline__ double self_pair_term(T mk, T gk, T eps2) {
   return double(y3) * double(delta);
 }
 
+// The FP32 VJP pair in split form.  The row term y3 (h - 3 y2 (e.h) e) is
+// linear in h = m_k gbar_j - m_j gbar_k, so a chunk of sources accumulates
+//   a = sum y3 gbar_j,   b = sum y3 m_j,   c = sum y3 (y2 (e.h)) e,
+//   dm = sum y3 (gbar_j . e)                   (y = s^-1/2, y2 = y^2, y3 = y^3)
+// and the target adds m_k a - gbar_k b - 3 c once per chunk (vjp_split_flush).
+// e.h is formed as m_k (gbar_j . e) - m_j (gbar_k . e), reusing the mass
+// term's dot product: 26 operations per pair (10 two-operand, 16 FMA) where
+// forming h per pair takes 29 (12 and 17).  The error of each sum stays
+// within u32 times the sum of its terms' magnitudes, which m_k, |gbar_k| and
+// 3 scale to the same s^-3/2 (m_k |gbar_j| + m_j |gbar_k|) budget as before.
+// y2 (e.h) <= |e| H / s <= H / (2 eps) with H = m_k |gbar_j| + m_j |gbar_k|,
+// and y3 times it at most 0.29 eps^-4 H, so the FP32 form needs eps^-4 H
+// below FLT_MAX.  `drop` zeroes the pair (y = 0): the self pair j == k,
+// whose y3 m_k gbar_k in a and y3 m_k in b cancel in the flush only up to the
+// rounding of those sums, so it is left out instead.
+struct VjpSplit {
+  float ax, ay, az, b, cx, cy, cz, dm;
+};
+
+__device__ __forceinline__ void vjp_split_zero(VjpSplit &a) {
+  a.ax = a.ay = a.az = a.b = 0.0f;
+  a.cx = a.cy = a.cz = a.dm = 0.0f;
+}
+
+__device__ __forceinline__ void vjp_pair_split(float ex, float ey, float ez,
+                                               float mj, float gjx, float gjy,
+                                               float gjz, float mk, float gkx,
+                                               float gky, float gkz,
+                                               float eps2, bool drop,
+                                               VjpSplit &a) {
+  float s = fmaf(ex, ex, eps2);
+  s = fmaf(ey, ey, s);
+  s = fmaf(ez, ez, s);
+  const float y = drop ? 0.0f : rsqrt_f32(s);
+  const float y2 = y * y;
+  const float y3 = y2 * y;
+  const float ge = fmaf(gjz, ez, fmaf(gjy, ey, gjx * ex));
+  const float ek = fmaf(gkz, ez, fmaf(gky, ey, gkx * ex));
+  const float eh = fmaf(mk, ge, -(mj * ek));
+  const float w = y3 * (y2 * eh);
+  a.dm = fmaf(ge, y3, a.dm);
+  a.ax = fmaf(y3, gjx, a.ax);
+  a.ay = fmaf(y3, gjy, a.ay);
+  a.az = fmaf(y3, gjz, a.az);
+  a.b = fmaf(y3, mj, a.b);
+  a.cx = fmaf(w, ex, a.cx);
+  a.cy = fmaf(w, ey, a.cy);
+  a.cz = fmaf(w, ez, a.cz);
+}
+
+// The chunk's row terms m_k a - gbar_k b - 3 c (and dm), added to the FP64
+// accumulators of the target.
+__device__ __forceinline__ void vjp_split_flush(const VjpSplit &a, float mk,
+                                                float gkx, float gky,
+                                                float gkz, double &sx,
+                                                double &sy, double &sz,
+                                                double &sm) {
+  sx += double(fmaf(-3.0f, a.cx, fmaf(mk, a.ax, -(gkx * a.b))));
+  sy += double(fmaf(-3.0f, a.cy, fmaf(mk, a.ay, -(gky * a.b))));
+  sz += double(fmaf(-3.0f, a.cz, fmaf(mk, a.az, -(gkz * a.b))));
+  sm += double(a.dm);
+}
+
 // ------------------------------------------------------ source tile layout --
 
 // NBODY_MIXED_DS splits a coordinate v into two FP32 numbers, hi = fl32(v)

@@ -24,6 +24,7 @@
 // G sum_j m_j d s^-3/2 and the reciprocal square root from the hardware
 // approximation (v_rsq_f32 / v_rsq_f64), refined in FP64 by one third-order step.
 #include <algorithm>
+#include <type_traits>
 
 #include "nbody_device.h"
 
@@ -193,10 +194,20 @@ __global__ __launch_bounds__(kThreads) void accel_kernel(
 
 // ---------------------------------------------------------------------- VJP --
 
+// Resident waves per SIMD the VJP kernels are compiled for.  Left free, the
+// compiler hoists a whole chunk's LDS reads in the FP32-pair kernels and needs
+// up to 106 VGPRs (4 waves); held to 8 waves (64 VGPRs) they lose nothing
+// and do not spill, except the D64 kernel at L = 16 (77 VGPRs, 6 waves, no
+// spill).  FP64 (two targets per lane, about 90 VGPRs) is left to the
+// compiler.
+constexpr int vjp_waves(int prec, int L) {
+  return prec == NBODY_FP64 ? 1 : (prec == NBODY_MIXED_D64 && L == 16 ? 6 : 8);
+}
+
 // Rows as in accel_kernel: targets k = row0 .. row0 + nt - 1, sources all n
 // bodies (with their dL/da), output row k - row0 of stride nt.
 template <int PREC, int R, int L>
-__global__ __launch_bounds__(kThreads) void vjp_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(vjp_waves(PREC, L)))) void vjp_kernel(
     int n, int row0, int nt, const double *__restrict__ pos,
     const double *__restrict__ mass, const double *__restrict__ gacc,
     double eps2d, double scale, int jchunk, double *__restrict__ out_x,
@@ -274,37 +285,47 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
       }
     } else {
       const float eps2 = float(eps2d);
-      for (int u0 = 0; u0 < PER; u0 += C) {
-        float fx[R], fy[R], fz[R], fm[R];
+      // Tiles that hold some of this workgroup's own targets drop their self
+      // pairs (vjp_pair_split); every other tile runs without the test.
+      const int kblk = row0 + blockIdx.x * (G * R);
+      const bool diag = jt < kblk + G * R && jt + kThreads > kblk;
+      auto tile_pass = [&](auto diag_tag) {
+        constexpr bool D = decltype(diag_tag)::value;
+        for (int u0 = 0; u0 < PER; u0 += C) {
+          VjpSplit acc[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) fx[r] = fy[r] = fz[r] = fm[r] = 0.0f;
+          for (int r = 0; r < R; ++r) vjp_split_zero(acc[r]);
 #pragma unroll
-        for (int u = 0; u < C; ++u) {
-          const VSrc<PREC> s = tile[(u0 + u) * L + q];
+          for (int u = 0; u < C; ++u) {
+            const VSrc<PREC> s = tile[(u0 + u) * L + q];
+            const int j = jt + (u0 + u) * L + q;
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            float ex, ey, ez;
-            if constexpr (PREC == NBODY_MIXED_DS) {
-              ex = ds_diff(s.x, s.xl, xk[r], xl[r]);
-              ey = ds_diff(s.y, s.yl, yk[r], yl[r]);
-              ez = ds_diff(s.z, s.zl, zk[r], zl[r]);
-            } else {
-              ex = DT(s.x - xk[r]);
-              ey = DT(s.y - yk[r]);
-              ez = DT(s.z - zk[r]);
+            for (int r = 0; r < R; ++r) {
+              float ex, ey, ez;
+              if constexpr (PREC == NBODY_MIXED_DS) {
+                ex = ds_diff(s.x, s.xl, xk[r], xl[r]);
+                ey = ds_diff(s.y, s.yl, yk[r], yl[r]);
+                ez = ds_diff(s.z, s.zl, zk[r], zl[r]);
+              } else {
+                ex = DT(s.x - xk[r]);
+                ey = DT(s.y - yk[r]);
+                ez = DT(s.z - zk[r]);
+              }
+              vjp_pair_split(ex, ey, ez, s.m, s.gx, s.gy, s.gz, mk[r],
+                             gkx[r], gky[r], gkz[r], eps2,
+                             D && j == row0 + kbase + r * G, acc[r]);
             }
-            vjp_pair<float>(ex, ey, ez, s.m, s.gx, s.gy, s.gz, mk[r], gkx[r],
-                            gky[r], gkz[r], eps2, fx[r], fy[r], fz[r], fm[r]);
           }
-        }
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          sx[r] += double(fx[r]);
-          sy[r] += double(fy[r]);
-          sz[r] += double(fz[r]);
-          sm[r] += double(fm[r]);
+          for (int r = 0; r < R; ++r)
+            vjp_split_flush(acc[r], mk[r], gkx[r], gky[r], gkz[r], sx[r],
+                            sy[r], sz[r], sm[r]);
         }
-      }
+      };
+      if (diag)
+        tile_pass(std::true_type{});
+      else
+        tile_pass(std::false_type{});
     }
   }
 
@@ -320,7 +341,8 @@ __global__ __launch_bounds__(kThreads) void vjp_kernel(
     const int k = kbase + r * G;
     const int gk = row0 + k;
     if (q == 0 && k < nt) {
-      if (gk >= jbeg && gk < jend) {  // this split holds the self pair
+      // the FP64 path's self pair (the FP32 ones drop theirs)
+      if (PREC == NBODY_FP64 && gk >= jbeg && gk < jend) {
         tx -= self_pair_term<AT>(mk[r], gkx[r], eps2a);
         ty -= self_pair_term<AT>(mk[r], gky[r], eps2a);
         tz -= self_pair_term<AT>(mk[r], gkz[r], eps2a);
@@ -650,7 +672,14 @@ hipError_t launch_vjp_p(const Plan &pl, int n, int row0, int nt,
 #define NBODY_VJP_CALL(R_, L_)                                               \
   vjp_kernel<PREC, R_, L_><<<grid, kThreads, 0, st>>>(                      \
       n, row0, nt, pos, mass, gacc, eps2, scale, jc, ox, om, stride)
-  NBODY_RL_SWITCH(pl.R, pl.L, NBODY_VJP_CALL);
+  // the shapes the VJP plans use: two targets per lane for FP64, one for
+  // the FP32-pair modes; 1, 4 or 16 lanes per target
+  constexpr int R = PREC == NBODY_FP64 ? 2 : 1;
+  if (pl.R != R) return hipErrorInvalidValue;
+  if (pl.L == 1) NBODY_VJP_CALL(R, 1);
+  else if (pl.L == 4) NBODY_VJP_CALL(R, 4);
+  else if (pl.L == 16) NBODY_VJP_CALL(R, 16);
+  else return hipErrorInvalidValue;
 #undef NBODY_VJP_CALL
   return hipGetLastError();
 }

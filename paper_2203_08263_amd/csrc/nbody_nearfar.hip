@@ -489,57 +489,65 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
     if constexpr (NEAR64) if (all_far) {
       // every run of this tile is far for the wave: no per-chunk decisions
       for (int u0 = 0; u0 < PER; u0 += C) {
-        float fx = 0.0f, fy = 0.0f, fz = 0.0f, fm = 0.0f;
+        VjpSplit acc;
+        vjp_split_zero(acc);
 #pragma unroll
         for (int u = 0; u < C; ++u) {
           const VSrc<NBODY_MIXED> s = far_tile[(u0 + u) * L + q];
-          vjp_pair<float>(s.x - xr, s.y - yr, s.z - zr, s.m, s.gx, s.gy, s.gz,
-                          mk, gkx, gky, gkz, eps2, fx, fy, fz, fm);
+          vjp_pair_split(s.x - xr, s.y - yr, s.z - zr, s.m, s.gx, s.gy, s.gz,
+                         mk, gkx, gky, gkz, eps2, false, acc);
         }
-        sx += double(fx);
-        sy += double(fy);
-        sz += double(fz);
-        sm += double(fm);
+        vjp_split_flush(acc, mk, gkx, gky, gkz, sx, sy, sz, sm);
       }
       continue;
     }
-    for (int u0 = 0; u0 < PER; u0 += C) {
-      const bool far = (far_mask >> (u0 / C)) & 1u;
-      if constexpr (NEAR64) {
-        if (!far) {
+    // Tiles that hold some of this workgroup's own targets: the FP32 near
+    // runs drop their self pairs (vjp_pair_split); far runs never hold one.
+    const int kblk = row0 + blockIdx.x * G;
+    const bool diag = jt < kblk + G && jt + kThreads > kblk;
+    auto tile_pass = [&](auto diag_tag) {
+      constexpr bool D = decltype(diag_tag)::value;
+      for (int u0 = 0; u0 < PER; u0 += C) {
+        const bool far = (far_mask >> (u0 / C)) & 1u;
+        if constexpr (NEAR64) {
+          if (!far) {
 #pragma unroll 2
+            for (int u = 0; u < C; ++u) {
+              const NearSrc s = near_tile[(u0 + u) * L + q];
+              vjp_pair<double>(s.x - xk, s.y - yk, s.z - zk, double(s.m),
+                               double(s.gx), double(s.gy), double(s.gz), mk64,
+                               gkx64, gky64, gkz64, eps2d, sx, sy, sz, sm);
+            }
+            continue;
+          }
+        }
+        VjpSplit acc;
+        vjp_split_zero(acc);
+        if (far) {
+#pragma unroll
+          for (int u = 0; u < C; ++u) {
+            const VSrc<NBODY_MIXED> s = far_tile[(u0 + u) * L + q];
+            vjp_pair_split(s.x - xr, s.y - yr, s.z - zr, s.m, s.gx, s.gy,
+                           s.gz, mk, gkx, gky, gkz, eps2, false, acc);
+          }
+        } else if constexpr (!NEAR64) {
+#pragma unroll
           for (int u = 0; u < C; ++u) {
             const NearSrc s = near_tile[(u0 + u) * L + q];
-            vjp_pair<double>(s.x - xk, s.y - yk, s.z - zk, double(s.m),
-                             double(s.gx), double(s.gy), double(s.gz), mk64,
-                             gkx64, gky64, gkz64, eps2d, sx, sy, sz, sm);
+            const VSrc<NBODY_MIXED> f = far_tile[(u0 + u) * L + q];
+            const int j = jt + (u0 + u) * L + q;
+            vjp_pair_split(float(s.x - xk), float(s.y - yk), float(s.z - zk),
+                           f.m, f.gx, f.gy, f.gz, mk, gkx, gky, gkz, eps2,
+                           D && j == gk, acc);
           }
-          continue;
         }
+        vjp_split_flush(acc, mk, gkx, gky, gkz, sx, sy, sz, sm);
       }
-      float fx = 0.0f, fy = 0.0f, fz = 0.0f, fm = 0.0f;
-      if (far) {
-#pragma unroll
-        for (int u = 0; u < C; ++u) {
-          const VSrc<NBODY_MIXED> s = far_tile[(u0 + u) * L + q];
-          vjp_pair<float>(s.x - xr, s.y - yr, s.z - zr, s.m, s.gx, s.gy, s.gz,
-                          mk, gkx, gky, gkz, eps2, fx, fy, fz, fm);
-        }
-      } else if constexpr (!NEAR64) {
-#pragma unroll
-        for (int u = 0; u < C; ++u) {
-          const NearSrc s = near_tile[(u0 + u) * L + q];
-          const VSrc<NBODY_MIXED> f = far_tile[(u0 + u) * L + q];
-          vjp_pair<float>(float(s.x - xk), float(s.y - yk), float(s.z - zk),
-                          f.m, f.gx, f.gy, f.gz, mk, gkx, gky, gkz, eps2, fx,
-                          fy, fz, fm);
-        }
-      }
-      sx += double(fx);
-      sy += double(fy);
-      sz += double(fz);
-      sm += double(fm);
-    }
+    };
+    if (!NEAR64 && diag)
+      tile_pass(std::true_type{});
+    else
+      tile_pass(std::false_type{});
   }
 
   double *ox = out_x + size_t(blockIdx.y) * split_stride;
@@ -549,17 +557,13 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
   double tz = group_sum<L>(sz);
   const double tm = group_sum<L>(sm);
   if (q == 0 && ok) {
-    if (gk >= jbeg && gk < jend) {  // this split holds the self pair (e = 0),
-      // always in a near run (its run box contains x_k, gap 0)
-      if constexpr (NEAR64) {
-        tx -= self_pair_term<double>(mk64, gkx64, eps2d);
-        ty -= self_pair_term<double>(mk64, gky64, eps2d);
-        tz -= self_pair_term<double>(mk64, gkz64, eps2d);
-      } else {
-        tx -= self_pair_term<float>(mk, gkx, eps2);
-        ty -= self_pair_term<float>(mk, gky, eps2);
-        tz -= self_pair_term<float>(mk, gkz, eps2);
-      }
+    // this split holds the self pair (e = 0), always in a near run (its run
+    // box contains x_k, gap 0): FP64 there for NBODY_MIXED_NF64, dropped by
+    // the FP32 near runs otherwise
+    if (NEAR64 && gk >= jbeg && gk < jend) {
+      tx -= self_pair_term<double>(mk64, gkx64, eps2d);
+      ty -= self_pair_term<double>(mk64, gky64, eps2d);
+      tz -= self_pair_term<double>(mk64, gkz64, eps2d);
     }
     ox[k] = scale * tx;
     ox[nt + k] = scale * ty;

@@ -281,6 +281,43 @@ def test_fp32_pair_modes_accept_the_smallest_eps(B):
         assert rc == 2, lib.nbody_last_error().decode()
 
 
+@pytest.mark.parametrize("prec", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("eps", [2.0 ** -42, 1e-11, 2.0 ** -32 * 0.999])
+def test_fp32_vjp_rejects_eps_below_its_range(B, prec, eps):
+    """The FP32 VJP pair forms s^-5/2 (e.h) before it multiplies by e; over
+    all pair distances that reaches 0.29 eps^-4 H, so the VJP calls take
+    eps >= 2^-32 in the FP32 pair modes, while the forward calls still take
+    eps down to 2^-42."""
+    lib = B.load_library()
+    n = 1000
+    assert lib.nbody_accel_vjp(n, _p(FAKE), _p(FAKE), _p(FAKE), _p(FAKE), _p(FAKE),
+                               _params(B, eps=eps), prec, _p(FAKE), 1 << 30, None) == 1
+    assert "(VJP)" in lib.nbody_last_error().decode()
+    assert lib.nbody_accel_vjp_rows(n, 0, 10, _p(FAKE), _p(FAKE), _p(FAKE), _p(FAKE),
+                                    _p(FAKE), _params(B, eps=eps), prec, _p(FAKE),
+                                    1 << 30, None) == 1
+    assert "(VJP)" in lib.nbody_last_error().decode()
+    assert lib.nbody_step_adjoint(n, 10, 5, _p(FAKE), _p(FAKE), _params(B, eps=eps),
+                                  prec, 0, _p(FAKE), _p(FAKE), None, _p(FAKE),
+                                  _p(FAKE), 1 << 30, None) == 1
+    assert "(VJP)" in lib.nbody_last_error().decode()
+    # the forward call passes the eps check and fails on the missing workspace
+    assert _accel(B, n=65536, prec=prec, eps=eps, ws=None, wsb=0) == 2
+    # FP64 VJP: past the eps check, fails on the missing workspace
+    assert lib.nbody_accel_vjp(65536, _p(FAKE), _p(FAKE), _p(FAKE), _p(FAKE), _p(FAKE),
+                               _params(B, eps=eps), 0, None, 0, None) == 2
+
+
+def test_fp32_vjp_accepts_the_smallest_eps(B):
+    lib = B.load_library()
+    assert "#define NBODY_MIN_EPS_FP32_VJP (0x1p-32)" in open(HEADER).read()
+    for prec in (1, 2, 3, 4, 5):
+        rc = lib.nbody_accel_vjp(65536, _p(FAKE), _p(FAKE), _p(FAKE), _p(FAKE),
+                                 _p(FAKE), _params(B, eps=2.0 ** -32), prec, None, 0,
+                                 None)
+        assert rc == 2, lib.nbody_last_error().decode()
+
+
 def test_auto_checkpoint_interval_fits_the_budget(B):
     from paper_2203_08263_amd import auto_ckpt_every
     assert auto_ckpt_every(8192, 50) == 1               # every state fits in 1 GiB

@@ -181,6 +181,40 @@ def test_vjp_parity(B, dev, oracle, prec, n):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_vjp_edge_cases(B, dev, oracle, prec):
+    say("vjp edge cases", prec)
+    # one body: its only pair is the self pair, which adds nothing
+    gx, gm = B.nbody_accel_vjp(T([[0.3], [-0.2], [0.9]], dev), T([5.0], dev),
+                               T([[1.0], [2.0], [-3.0]], dev), 1.0, 1e-3, prec)
+    assert np.all(N(gx) == 0.0) and np.all(N(gm) == 0.0)
+    # coincident distinct bodies (e = 0, but h = m_k g_j - m_j g_k is not),
+    # a zero-mass body and a zero upstream gradient
+    pos = np.array([[0.1, 0.1, -0.5, 0.7, 0.1], [0.2, 0.2, 0.1, 0.0, 0.2],
+                    [0.0, 0.0, 0.3, 0.1, 0.0]])
+    mass = np.array([1.0, 2.0, 0.0, 0.5, 0.25])
+    g = np.array([[1.0, -2.0, 0.5, 0.0, 3.0], [0.5, 1.0, -1.0, 0.0, 0.0],
+                  [-1.0, 0.25, 2.0, 0.0, 1.0]])
+    for eps in (1e-2, 2.0 ** -32):
+        rx, rm = oracle.accel_vjp(pos, mass, g, 1.0, eps)
+        gx, gm = B.nbody_accel_vjp(T(pos, dev), T(mass, dev), T(g, dev), 1.0, eps, prec)
+        bx, bm = _tol.vjp_bound(pos, mass, g, 1.0, eps, prec)
+        _check_bound(N(gx), rx, bx, prec + " dL/dx eps %g" % eps)
+        assert np.all(np.abs(N(gm) - rm) <= bm), prec + " dL/dm eps %g" % eps
+    # a pair at distance eps / 2, where the e term's weight s^-5/2 |e| peaks,
+    # at the smallest eps the FP32 VJP accepts: finite, and within the bound
+    eps = 2.0 ** -32
+    pos = np.array([[0.5, 0.5 + eps / 2], [0.25, 0.25], [-0.125, -0.125]])
+    mass = np.array([1.0, 1.0])
+    g = np.array([[1.0, -1.0], [0.5, 0.5], [0.0, 1.0]])
+    rx, rm = oracle.accel_vjp(pos, mass, g, 1.0, eps)
+    gx, gm = B.nbody_accel_vjp(T(pos, dev), T(mass, dev), T(g, dev), 1.0, eps, prec)
+    assert np.all(np.isfinite(N(gx))) and np.all(np.isfinite(N(gm)))
+    bx, bm = _tol.vjp_bound(pos, mass, g, 1.0, eps, prec)
+    _check_bound(N(gx), rx, bx, prec + " dL/dx close pair")
+    assert np.all(np.abs(N(gm) - rm) <= bm), prec + " dL/dm close pair"
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_vjp_translation_and_homogeneity(B, dev, prec):
     say("vjp invariants", prec)
     pos, _, mass = inputs.uniform_cube(2000, 8)

@@ -45,7 +45,9 @@ def _direct_vjp(pos, mass, g, G, eps, prec, rows):
         tx = y3 * H * (12.0 * delta / np.sqrt(s) + (40 + L) * u * 4.0)
         tm = y3 * gn * (4.0 * delta + (16 + L) * u * en)
         tx[k] = tm[k] = 0.0
-        self_res = u * eps ** -3 * u * mass[k] * gn[k]
+        # the FP64 pairs' self-pair residue (the FP32 pairs drop the self pair)
+        self_res = (u * eps ** -3 * u * mass[k] * gn[k]
+                    if prec in ("fp64", "mixed_nf64") else 0.0)
         bx.append(_tol.SAFETY * abs(G) * (tx.sum() + self_res))
         bm.append(_tol.SAFETY * abs(G) * tm.sum())
     return np.array(bx), np.array(bm)
@@ -154,3 +156,78 @@ def test_near_far_recentred_difference_within_delta():
     got = ((xj - c).astype(np.float32) - (xi - c).astype(np.float32)).astype(np.float64)
     bound = _tol.NF_DELTA * _tol.U32 * np.linalg.norm(d, axis=0)
     assert _worst(got - d, bound) <= 1.0
+
+
+# ------------------------------------------------------------------------
+# The FP32 VJP pair arithmetic (split form) against the arithmetic part of
+# vjp_bound: chunks of VJP_CHUNK32 sources around one target, every
+# operation rounded to FP32 as the kernels round it (an FMA of FP32 operands
+# is exact in FP64 up to its one final rounding), the hardware reciprocal
+# square root taken as the correctly rounded value times (1 + r) with
+# |r| <= 2^-23.3, its measured worst relative error.
+
+def _f(x):
+    return np.float32(x)
+
+
+def _fma(a, b, c):
+    return np.float32(np.float64(a) * np.float64(b) + np.float64(c))
+
+
+def _split_chunk(e, mj, gj, mk, gk, eps2, r):
+    """dL/dx_k contribution of one chunk, FP32 split-form arithmetic."""
+    acc = np.zeros(8, dtype=np.float32)             # ax ay az b cx cy cz dm
+    for u in range(e.shape[1]):
+        ex, ey, ez = (_f(v) for v in e[:, u])
+        s = _fma(ex, ex, eps2)
+        s = _fma(ey, ey, s)
+        s = _fma(ez, ez, s)
+        y = _f(np.float64(_f(1.0 / np.sqrt(np.float64(s)))) * (1.0 + r[u]))
+        y2 = _f(y * y)
+        y3 = _f(y2 * y)
+        gx, gy, gz = (_f(v) for v in gj[:, u])
+        ge = _fma(gz, ez, _fma(gy, ey, _f(gx * ex)))
+        ek = _fma(gk[2], ez, _fma(gk[1], ey, _f(gk[0] * ex)))
+        eh = _fma(mk, ge, -_f(mj[u] * ek))
+        w = _f(y3 * _f(y2 * eh))
+        acc[7] = _fma(ge, y3, acc[7])
+        acc[0] = _fma(y3, gx, acc[0])
+        acc[1] = _fma(y3, gy, acc[1])
+        acc[2] = _fma(y3, gz, acc[2])
+        acc[3] = _fma(y3, mj[u], acc[3])
+        acc[4] = _fma(w, ex, acc[4])
+        acc[5] = _fma(w, ey, acc[5])
+        acc[6] = _fma(w, ez, acc[6])
+    return np.array([np.float64(_fma(_f(-3.0), acc[4 + c],
+                                     _fma(mk, acc[c], -_f(gk[c] * acc[3]))))
+                     for c in range(3)])
+
+
+def test_vjp_split_pair_arithmetic_within_bound():
+    rng = np.random.default_rng(5)
+    L = _tol.VJP_CHUNK32
+    worst = 0.0
+    for t in range(300):
+        eps = 10.0 ** rng.uniform(-4, -1)
+        eps2 = _f(eps * eps)
+        scale = 10.0 ** rng.uniform(-4, 1)          # source distances
+        e = (rng.normal(size=(3, L)) * scale).astype(np.float32).astype(np.float64)
+        if t % 3 == 0:
+            e[:, : L // 4] *= 1e-3                  # a few close sources
+        mj = (10.0 ** rng.uniform(-3, 0, L)).astype(np.float32)
+        gj = rng.normal(size=(3, L)).astype(np.float32).astype(np.float64)
+        mk = _f(10.0 ** rng.uniform(-3, 0))
+        gk = rng.normal(size=3).astype(np.float32)
+        r = rng.uniform(-1, 1, L) * 2.0 ** -23.3
+        got = _split_chunk(e, mj, gj, mk, gk, eps2, r)
+        # exact row terms in FP64 from the same FP32 inputs
+        s = (e * e).sum(axis=0) + np.float64(eps2)
+        y3 = s ** -1.5
+        h = np.float64(mk) * gj - mj.astype(np.float64) * gk.astype(np.float64)[:, None]
+        eh = (e * h).sum(axis=0)
+        ref = (y3 * (h - 3.0 * eh * e / s)).sum(axis=1)
+        H = np.float64(mk) * np.linalg.norm(gj, axis=0) + \
+            mj * np.linalg.norm(gk.astype(np.float64))
+        bound = 4.0 * (40 + L) * _tol.U32 * (y3 * H).sum()
+        worst = max(worst, np.linalg.norm(got - ref) / bound)
+    assert worst <= 1.0, worst
