@@ -36,6 +36,9 @@ NBODY_OP_DIAGNOSTICS = 4
 NBODY_OP_MORTON_SORT = 5
 NBODY_MAX_N = 1 << 28
 NBODY_NOALLOC_SCRATCH_BYTES = 64 << 20
+# smallest eps of the FP32-pair precisions: every call / the VJP calls
+NBODY_MIN_EPS_FP32 = 2.0 ** -42
+NBODY_MIN_EPS_FP32_VJP = 2.0 ** -32
 
 SYMBOLS = ("nbody_workspace_bytes", "nbody_checkpoint_bytes", "nbody_accel",
            "nbody_step", "nbody_accel_vjp", "nbody_step_adjoint",

@@ -310,7 +310,9 @@ def test_fp32_vjp_rejects_eps_below_its_range(B, prec, eps):
 
 def test_fp32_vjp_accepts_the_smallest_eps(B):
     lib = B.load_library()
-    assert "#define NBODY_MIN_EPS_FP32_VJP (0x1p-32)" in open(HEADER).read()
+    txt = open(HEADER).read()
+    assert "#define NBODY_MIN_EPS_FP32_VJP (0x1p-32)" in txt
+    assert B.NBODY_MIN_EPS_FP32_VJP == 2.0 ** -32 and B.NBODY_MIN_EPS_FP32 == 2.0 ** -42
     for prec in (1, 2, 3, 4, 5):
         rc = lib.nbody_accel_vjp(65536, _p(FAKE), _p(FAKE), _p(FAKE), _p(FAKE),
                                  _p(FAKE), _params(B, eps=2.0 ** -32), prec, None, 0,
