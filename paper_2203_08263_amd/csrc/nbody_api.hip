@@ -72,29 +72,42 @@ Plan make_plan(KernelKind kind, int precision, int64_t nt, int64_t n) {
 
 Plan make_plan_general(KernelKind kind, int precision, int64_t nt, int64_t n) {
   // Chosen from launch-shape sweeps on MI355X (all-pairs kernel plus split
-  // reduction).  Targets per lane R: 2 for FP64, 1 for the FP32-pair modes
-  // (their pair chain is latency-bound, so more resident waves beat more
-  // independent chains per lane).  About 8192 workgroups (32 per CU: 8
-  // resident waves per SIMD, several rounds of them), reached with the
-  // smallest lanes-per-target L in {1, 4, 16} that needs at most 64 source
-  // splits, each at least one 256-body tile long.  Target blocks count the
-  // nt target rows, source splits the n source bodies.  NBODY_MIXED_NF64
-  // starts at L = 4: its near runs are FP64 pairs, and the finer target
-  // waves and source runs of L = 4 leave fewer pairs near (measured: +21 %
-  // forward at N = 65536, +8 % at 262144, equal at 16384; L = 16 is slower
-  // for both near / far modes).
-  const int R = (precision == NBODY_FP64 && kind != kPotential) ? 2 : 1;
+  // reduction).  About 8192 workgroups (32 per CU: 8 resident waves per SIMD,
+  // several rounds of them), reached with the smallest lanes-per-target L in
+  // {1, 4, 16} that needs at most 64 source splits, each at least one
+  // 256-body tile long.  Target blocks count the nt target rows, source
+  // splits the n source bodies.  Targets per lane R: 2 for the FP64 force, 1
+  // for the FP32-pair modes (their pair chain is latency-bound, so more
+  // resident waves beat more independent chains per lane).  The FP64 VJP
+  // takes R = 1 (its split-form sums, 8 FP64 values per target, would need
+  // 162 VGPRs for two targets) unless that needs L = 16 (small systems):
+  // there a lane's 16 sources per tile leave too little work between the
+  // tile barriers (measured: -12 % at N = 2048, -37 % at 8192), and R = 2
+  // with h formed per pair is faster.  NBODY_MIXED_NF64 starts at L = 4: its
+  // near runs are FP64 pairs, and the finer target waves and source runs of
+  // L = 4 leave fewer pairs near (measured: +21 % forward at N = 65536, +8 %
+  // at 262144, equal at 16384; L = 16 is slower for both near / far modes).
   const int64_t target = 8192, max_sj = 64;
   const int64_t ntiles = (n + kThreads - 1) / kThreads;
-  Plan p{};
-  for (int L : {1, 4, 16}) {
-    if (precision == NBODY_MIXED_NF64 && L < 4) continue;
-    const int64_t per_block = int64_t(kThreads / L) * R;
-    p.R = R;
-    p.L = L;
-    p.n_ib = (nt + per_block - 1) / per_block;
-    p.sj = (target + p.n_ib - 1) / p.n_ib;
-    if (p.sj <= std::min(max_sj, ntiles)) break;
+  auto shape = [&](int R) {
+    Plan p{};
+    for (int L : {1, 4, 16}) {
+      if (precision == NBODY_MIXED_NF64 && L < 4) continue;
+      const int64_t per_block = int64_t(kThreads / L) * R;
+      p.R = R;
+      p.L = L;
+      p.n_ib = (nt + per_block - 1) / per_block;
+      p.sj = (target + p.n_ib - 1) / p.n_ib;
+      if (p.sj <= std::min(max_sj, ntiles)) break;
+    }
+    return p;
+  };
+  Plan p;
+  if (precision == NBODY_FP64 && kind == kAccel) {
+    p = shape(2);
+  } else {
+    p = shape(1);
+    if (precision == NBODY_FP64 && kind == kVjp && p.L == 16) p = shape(2);
   }
   p.sj = std::max<int64_t>(1, std::min({p.sj, ntiles, max_sj}));
   const int64_t tiles_per_split = (ntiles + p.sj - 1) / p.sj;

@@ -102,7 +102,9 @@ __device__ __forceinline__ void chunk_sum_f32(SrcF src, float eps2, float &fx,
   }
 }
 
-// One source j against target k for the VJP (row formulation):
+// One source j against target k for the VJP (row formulation), with h formed
+// per pair (the FP64 near runs of NBODY_MIXED_NF64; every other VJP pair
+// takes the split form below):
 //   g += s^-3/2 (h + t e),  t = -3 (e.h) / s,   dm += (gbar_j . e) s^-3/2
 // with e = x_j - x_k and h = m_k gbar_j - m_j gbar_k, formed as
 // fma(m_k, gbar_j, -(m_j gbar_k)).  For the self pair j == k that h is not
@@ -195,6 +197,41 @@ __device__ __forceinline__ void vjp_pair_split(float ex, float ey, float ez,
   a.cx = fmaf(w, ex, a.cx);
   a.cy = fmaf(w, ey, a.cy);
   a.cz = fmaf(w, ez, a.cz);
+}
+
+// The split-form pair in FP64 (the FP64 VJP): the same sums, in FP64
+// straight over the whole source range; the target forms its row from them
+// once, after the last source.  26 FP64 operations plus the reciprocal
+// square root instead of 29.
+struct VjpSplit64 {
+  double ax, ay, az, b, cx, cy, cz, dm;
+};
+
+__device__ __forceinline__ void vjp_pair_split64(double ex, double ey,
+                                                 double ez, double mj,
+                                                 double gjx, double gjy,
+                                                 double gjz, double mk,
+                                                 double gkx, double gky,
+                                                 double gkz, double eps2,
+                                                 bool drop, VjpSplit64 &a) {
+  double s = fma(ex, ex, eps2);
+  s = fma(ey, ey, s);
+  s = fma(ez, ez, s);
+  const double y = drop ? 0.0 : rsqrt_f64(s);
+  const double y2 = y * y;
+  const double y3 = y2 * y;
+  const double ge = fma(gjz, ez, fma(gjy, ey, gjx * ex));
+  const double ek = fma(gkz, ez, fma(gky, ey, gkx * ex));
+  const double eh = fma(mk, ge, -(mj * ek));
+  const double w = y3 * (y2 * eh);
+  a.dm = fma(ge, y3, a.dm);
+  a.ax = fma(y3, gjx, a.ax);
+  a.ay = fma(y3, gjy, a.ay);
+  a.az = fma(y3, gjz, a.az);
+  a.b = fma(y3, mj, a.b);
+  a.cx = fma(w, ex, a.cx);
+  a.cy = fma(w, ey, a.cy);
+  a.cz = fma(w, ez, a.cz);
 }
 
 // The chunk's row terms m_k a - gbar_k b - 3 c (and dm), added to the FP64

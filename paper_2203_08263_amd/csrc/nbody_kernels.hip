@@ -198,8 +198,8 @@ __global__ __launch_bounds__(kThreads) void accel_kernel(
 // compiler hoists a whole chunk's LDS reads in the FP32-pair kernels and needs
 // up to 106 VGPRs (4 waves); held to 8 waves (64 VGPRs) they lose nothing
 // and do not spill, except the D64 kernel at L = 16 (77 VGPRs, 6 waves, no
-// spill).  FP64 (two targets per lane, about 90 VGPRs) is left to the
-// compiler.
+// spill).  FP64 (78 VGPRs and 6 waves at one target per lane, about 90 and
+// 5 at two) is left to the compiler: the split form spills at 7 or 8.
 constexpr int vjp_waves(int prec, int L) {
   return prec == NBODY_FP64 ? 1 : (prec == NBODY_MIXED_D64 && L == 16 ? 6 : 8);
 }
@@ -230,6 +230,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(vjp_wa
   float xl[R], yl[R], zl[R];  // lo parts (NBODY_MIXED_DS only)
   AT mk[R], gkx[R], gky[R], gkz[R];
   double sx[R], sy[R], sz[R], sm[R];
+  VjpSplit64 acc64[R];  // NBODY_FP64 only
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int k = kbase + r * G;
@@ -249,6 +250,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(vjp_wa
     gky[r] = ok ? AT(gacc[n + gk]) : AT(0);
     gkz[r] = ok ? AT(gacc[2 * n + gk]) : AT(0);
     sx[r] = sy[r] = sz[r] = sm[r] = 0.0;
+    acc64[r] = VjpSplit64{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   }
 
   for (int jt = jbeg; jt < jend; jt += kThreads) {
@@ -273,7 +275,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(vjp_wa
     tile[tid] = b;
     __syncthreads();
 
-    if constexpr (PREC == NBODY_FP64) {
+    if constexpr (PREC == NBODY_FP64 && R == 2) {
+      // two targets per lane (small systems): h formed per pair
 #pragma unroll 2
       for (int u = 0; u < PER; ++u) {
         const VSrc<PREC> s = tile[u * L + q];
@@ -283,6 +286,27 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(vjp_wa
                            s.gy, s.gz, mk[r], gkx[r], gky[r], gkz[r], eps2d,
                            sx[r], sy[r], sz[r], sm[r]);
       }
+    } else if constexpr (PREC == NBODY_FP64) {
+      // split form in FP64, self pairs dropped in the diagonal tiles as below
+      const int kblk = row0 + blockIdx.x * (G * R);
+      const bool diag = jt < kblk + G * R && jt + kThreads > kblk;
+      auto tile_pass64 = [&](auto diag_tag) {
+        constexpr bool D = decltype(diag_tag)::value;
+#pragma unroll 2
+        for (int u = 0; u < PER; ++u) {
+          const VSrc<PREC> s = tile[u * L + q];
+          const int j = jt + u * L + q;
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            vjp_pair_split64(s.x - xk[r], s.y - yk[r], s.z - zk[r], s.m, s.gx,
+                             s.gy, s.gz, mk[r], gkx[r], gky[r], gkz[r], eps2d,
+                             D && j == row0 + kbase + r * G, acc64[r]);
+        }
+      };
+      if (diag)
+        tile_pass64(std::true_type{});
+      else
+        tile_pass64(std::false_type{});
     } else {
       const float eps2 = float(eps2d);
       // Tiles that hold some of this workgroup's own targets drop their self
@@ -331,9 +355,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(vjp_wa
 
   double *ox = out_x + size_t(blockIdx.y) * split_stride;
   double *om = out_m + size_t(blockIdx.y) * split_stride;
-  const AT eps2a = AT(eps2d);
+  const double eps2a = eps2d;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
+    if constexpr (PREC == NBODY_FP64 && R == 1) {
+      const VjpSplit64 &a = acc64[r];
+      sx[r] = fma(-3.0, a.cx, fma(mk[r], a.ax, -(gkx[r] * a.b)));
+      sy[r] = fma(-3.0, a.cy, fma(mk[r], a.ay, -(gky[r] * a.b)));
+      sz[r] = fma(-3.0, a.cz, fma(mk[r], a.az, -(gkz[r] * a.b)));
+      sm[r] = a.dm;
+    }
     double tx = group_sum<L>(sx[r]);
     double ty = group_sum<L>(sy[r]);
     double tz = group_sum<L>(sz[r]);
@@ -341,11 +372,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(vjp_wa
     const int k = kbase + r * G;
     const int gk = row0 + k;
     if (q == 0 && k < nt) {
-      // the FP64 path's self pair (the FP32 ones drop theirs)
-      if (PREC == NBODY_FP64 && gk >= jbeg && gk < jend) {
-        tx -= self_pair_term<AT>(mk[r], gkx[r], eps2a);
-        ty -= self_pair_term<AT>(mk[r], gky[r], eps2a);
-        tz -= self_pair_term<AT>(mk[r], gkz[r], eps2a);
+      // the self pair: removed here after h formed per pair (FP64 with two
+      // targets per lane), dropped by the split-form pairs
+      if constexpr (PREC == NBODY_FP64 && R == 2) {
+        if (gk >= jbeg && gk < jend) {
+          tx -= self_pair_term<double>(mk[r], gkx[r], eps2a);
+          ty -= self_pair_term<double>(mk[r], gky[r], eps2a);
+          tz -= self_pair_term<double>(mk[r], gkz[r], eps2a);
+        }
       }
       ox[k] = scale * tx;
       ox[nt + k] = scale * ty;
@@ -672,14 +706,17 @@ hipError_t launch_vjp_p(const Plan &pl, int n, int row0, int nt,
 #define NBODY_VJP_CALL(R_, L_)                                               \
   vjp_kernel<PREC, R_, L_><<<grid, kThreads, 0, st>>>(                      \
       n, row0, nt, pos, mass, gacc, eps2, scale, jc, ox, om, stride)
-  // the shapes the VJP plans use: two targets per lane for FP64, one for
-  // the FP32-pair modes; 1, 4 or 16 lanes per target
-  constexpr int R = PREC == NBODY_FP64 ? 2 : 1;
-  if (pl.R != R) return hipErrorInvalidValue;
-  if (pl.L == 1) NBODY_VJP_CALL(R, 1);
-  else if (pl.L == 4) NBODY_VJP_CALL(R, 4);
-  else if (pl.L == 16) NBODY_VJP_CALL(R, 16);
-  else return hipErrorInvalidValue;
+  // the shapes the VJP plans use: one target per lane with 1, 4 or 16 lanes
+  // per target, and for small FP64 systems two targets per lane with 16
+  if (pl.R == 1 && pl.L == 1) NBODY_VJP_CALL(1, 1);
+  else if (pl.R == 1 && pl.L == 4) NBODY_VJP_CALL(1, 4);
+  else if (pl.R == 1 && pl.L == 16) NBODY_VJP_CALL(1, 16);
+  else if (pl.R == 2 && pl.L == 16) {
+    if constexpr (PREC == NBODY_FP64) NBODY_VJP_CALL(2, 16);
+    else return hipErrorInvalidValue;
+  } else {
+    return hipErrorInvalidValue;
+  }
 #undef NBODY_VJP_CALL
   return hipGetLastError();
 }

@@ -193,13 +193,15 @@ def vjp_bound(pos, mass, gacc, G, eps, precision, rows=None):
     (c = 40; the FP32 pairs sum y3 g_j, y3 m_j and y5 (e.h) e over a chunk
     and combine them with m_k, g_k and -3 at its end, each part carrying
     about 20 u of y3 H), plus the chunk summation as for the acceleration.
-    The self pair (e = 0) is left out of the sums.  The FP32 pairs drop it
-    (it adds exactly 0).  The FP64 pairs (fp64, and the near runs of
-    mixed_nf64) form h = fma(m_k, g_j, -(m_j g_k)), which for j == k is the
-    rounding error delta of m_k g_k (|delta| <= u m_k |g_k|), add
-    y3_self * delta with y3_self = eps^-3, and subtract the same product
-    afterwards; what remains is the rounding of that one addition, at most
-    u * eps^-3 * u * m_k |g_k| per row (added below)."""
+    The self pair (e = 0) is left out of the sums.  The split-form pairs
+    drop it (it adds exactly 0).  The FP64 pairs that form h per pair (the
+    FP64 VJP of small systems, two targets per lane, and the near runs of
+    mixed_nf64) form h = fma(m_k, g_j, -(m_j g_k)), which
+    for j == k is the rounding error delta of m_k g_k
+    (|delta| <= u64 m_k |g_k|), add y3_self * delta with y3_self = eps^-3,
+    and subtract the same product afterwards; what remains is the rounding
+    of that one addition, at most u64 * eps^-3 * u64 * m_k |g_k| per row
+    (added below)."""
     n = mass.size
     rows = np.arange(n) if rows is None else np.asarray(rows)
     v = vjp_sums(pos, mass, gacc, eps, rows)
@@ -229,7 +231,7 @@ def vjp_bound(pos, mass, gacc, G, eps, precision, rows=None):
         pm = 4.0 * (DS_DELTA * U32 * Be + DS_DELTA_X * U32 * U32 * (xk * Bsum + Bx))
     else:
         raise ValueError(precision)
-    self_res = (u * eps ** -3 * u * mk * gk
+    self_res = (U64 * eps ** -3 * U64 * mk * gk
                 if precision in ("fp64", "mixed_nf64") else 0.0)
     return (SAFETY * abs(G) * (px + ax + self_res),
             SAFETY * abs(G) * (pm + am))

@@ -45,8 +45,9 @@ def _direct_vjp(pos, mass, g, G, eps, prec, rows):
         tx = y3 * H * (12.0 * delta / np.sqrt(s) + (40 + L) * u * 4.0)
         tm = y3 * gn * (4.0 * delta + (16 + L) * u * en)
         tx[k] = tm[k] = 0.0
-        # the FP64 pairs' self-pair residue (the FP32 pairs drop the self pair)
-        self_res = (u * eps ** -3 * u * mass[k] * gn[k]
+        # FP64 pairs with h formed per pair leave a self-pair residue (the
+        # split-form pairs drop the self pair)
+        self_res = (_tol.U64 * eps ** -3 * _tol.U64 * mass[k] * gn[k]
                     if prec in ("fp64", "mixed_nf64") else 0.0)
         bx.append(_tol.SAFETY * abs(G) * (tx.sum() + self_res))
         bm.append(_tol.SAFETY * abs(G) * tm.sum())
