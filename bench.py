@@ -54,20 +54,14 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32, published
 PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64, published
 # Flops per body pair, counting add/sub/mul as 1, FMA as 2 and the reciprocal
 # square root as 2: the force pair (3 sub, 3 FMA, rsqrt, 3 mul, 3 FMA) is the
-# paper's 20.  The VJP pair of the FP32-pair modes, in split form (3 sub,
-# 3 FMA, rsqrt, 2 mul for y^2 and y^3, 1 mul + 2 FMA for gbar_j.e and again
-# for gbar_k.e, 1 mul + 1 FMA for e.h, 1 FMA for the mass term, 2 mul,
-# 3 + 1 + 3 FMA into the chunk sums) is 44; the FP64 VJP pair, with h formed
-# per pair (3 sub, 3 FMA, rsqrt, 2 mul, 3 mul + 3 FMA for h, 1 mul + 2 FMA
-# twice for e.h and gbar.e, 1 FMA, 2 mul, 6 FMA), is 48.
+# paper's 20.  The VJP pair, in the split form the kernels run (3 sub, 3 FMA,
+# rsqrt, 2 mul for y^2 and y^3, 1 mul + 2 FMA for gbar_j.e and again for
+# gbar_k.e, 1 mul + 1 FMA for e.h, 1 FMA for the mass term, 2 mul, 3 + 1 + 3
+# FMA into the sums) is 44 (48 with h formed per pair: 3 sub, 3 FMA, rsqrt,
+# 2 mul, 3 mul + 3 FMA for h, 1 mul + 2 FMA twice for e.h and gbar.e, 1 FMA,
+# 2 mul, 6 FMA).
 # The potential pair (diagnostics) is 3 sub, 3 FMA, rsqrt, 1 FMA = 13.
 FLOPS_PER_PAIR = {"accel": 20, "vjp": 44, "diag": 13}
-
-
-def flops_per_pair(kind, precision):
-    if kind == "vjp" and precision == "fp64":
-        return 48
-    return FLOPS_PER_PAIR[kind]
 DTYPE = {"fp64": "f64", "mixed": "f32-pair/f64-acc",
          "mixed_d64": "f32-pair(f64-diff)/f64-acc",
          "mixed_nf": "f32-pair(near f64-diff, far recentred)/f64-acc",
@@ -82,13 +76,13 @@ KERNEL_KIND = {"accel": "accel_kernel", "vjp": "vjp_kernel"}
 # kernel sources it was taken on (first 16 hex digits of their SHA-256) and
 # is reported as null for any other source.
 MEASURED_TRAFFIC = {
-    # profiles/vjp_nf_kernel_plummer262144_counters.md: 205.0 MB fetched +
+    # profiles/vjp_nf_kernel_plummer262144_counters.md: 203.8 MB fetched +
     # 67.1 MB written by the second vjp_nf_kernel launch
-    ("vjp", "mixed_nf", 262144): {"bytes": 272069563, "src_sha256": "08a8f602bc65859c"},
+    ("vjp", "mixed_nf", 262144): {"bytes": 270956105, "src_sha256": "5a3f8a684ea1652c"},
     # same file: 74.7 MB + 50.3 MB, accel_nf_kernel
-    ("accel", "mixed_nf", 262144): {"bytes": 125028147, "src_sha256": "08a8f602bc65859c"},
+    ("accel", "mixed_nf", 262144): {"bytes": 125011587, "src_sha256": "5a3f8a684ea1652c"},
     # profiles/accel_kernel_plummer65536_mixed.md: 16.8 MB + 50.3 MB
-    ("accel", "mixed", 65536): {"bytes": 67167332, "src_sha256": "08a8f602bc65859c"},
+    ("accel", "mixed", 65536): {"bytes": 67167300, "src_sha256": "5a3f8a684ea1652c"},
 }
 KERNEL_SRC = [os.path.join(ROOT, "paper_2203_08263_amd", "csrc", f)
               for f in ("nbody_kernels.hip", "nbody_nearfar.hip", "nbody_device.h")]
@@ -218,7 +212,7 @@ def roofline(torch, fn, n, kind, p, launches):
     far modes, the O(N) bounding-box pass)."""
     warm(torch, fn)
     ms = event_ms(torch, fn, launches)
-    flops = flops_per_pair(kind, p) * float(n) * n
+    flops = FLOPS_PER_PAIR[kind] * float(n) * n
     achieved = flops / (ms * 1e-3) / 1e12
     peak = PEAK_FP64_TFLOPS if p == "fp64" else PEAK_FP32_TFLOPS
     rec = MEASURED_TRAFFIC.get((kind, p, n))
@@ -231,7 +225,7 @@ def roofline(torch, fn, n, kind, p, launches):
             "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": traffic,
             "traffic_unit": "HBM bytes per launch", "avg_launch_ms": round(ms, 4),
-            "flops_per_pair": flops_per_pair(kind, p),
+            "flops_per_pair": FLOPS_PER_PAIR[kind],
             "algorithmic_flops_per_launch": flops}
 
 
@@ -341,7 +335,7 @@ def shape_legs(torch, B, inputs):
                 ms = event_ms(torch, fn, 20 if w.n <= 65536 else 8, warmup=0)
                 ips = float(rows) * w.n / (ms * 1e-3)
                 peak = PEAK_FP64_TFLOPS if p == "fp64" else PEAK_FP32_TFLOPS
-                fl = flops_per_pair(kind.replace("_share8", ""), p)
+                fl = FLOPS_PER_PAIR[kind.replace("_share8", "")]
                 res["%s_%s" % (kind, p)] = {
                     "ms": round(ms, 4), "G_int_s": round(ips / 1e9, 1),
                     "TFLOP_s": round(ips * fl / 1e12, 2),
