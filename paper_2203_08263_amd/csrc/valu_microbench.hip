@@ -71,6 +71,71 @@ __global__ __launch_bounds__(kThreads) void chains(int iters, T seed,
 // the shader-clock counter (clock64) and the constant-rate counter
 // (wall_clock64) at its start and end into stamp[4 * blockIdx.x ...], so the
 // host can derive the clock the chip ran at under this load.
+// The VJP pair of the library's FP32 kernels in split form (3 sub, 3 FMA,
+// rsq, 2 mul, g_j.e and g_k.e, e.h, 2 mul, 8 FMA into the sums: 26
+// operations + rsq), NCH independent chains per thread, the pair
+// difference taken from the chain's own c sums so every iteration depends
+// on the last.
+template <int NCH>
+__global__ __launch_bounds__(kThreads) void vjp_mix(int iters, float seed,
+                                                    float *__restrict__ out,
+                                                    unsigned long long *stamp) {
+  unsigned long long c0 = 0, w0 = 0;
+  if (threadIdx.x == 0) {
+    c0 = clock64();
+    w0 = wall_clock64();
+  }
+  const float xi = seed * float(threadIdx.x) * 1e-3f;
+  const float yi = -xi, zi = 0.5f * xi, eps2 = 1e-6f;
+  const float mk = 1e-4f, mj = 2e-4f, gkx = 0.3f, gky = -0.2f, gkz = 0.1f;
+  float ax[NCH], ay[NCH], az[NCH], b[NCH], cx[NCH], cy[NCH], cz[NCH], dm[NCH];
+#pragma unroll
+  for (int k = 0; k < NCH; ++k) {
+    ax[k] = ay[k] = az[k] = b[k] = dm[k] = 0.0f;
+    cx[k] = 0.25f + float(k);
+    cy[k] = -0.5f;
+    cz[k] = 0.75f - float(k);
+  }
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+      const float gjx = 0.5f + 0.1f * float(k), gjy = -0.25f, gjz = seed;
+      const float ex = cx[k] - xi, ey = cy[k] - yi, ez = cz[k] - zi;
+      float s = fmaf(ex, ex, eps2);
+      s = fmaf(ey, ey, s);
+      s = fmaf(ez, ez, s);
+      const float y = __builtin_amdgcn_rsqf(s);
+      const float y2 = y * y;
+      const float y3 = y2 * y;
+      const float ge = fmaf(gjz, ez, fmaf(gjy, ey, gjx * ex));
+      const float ek = fmaf(gkz, ez, fmaf(gky, ey, gkx * ex));
+      const float eh = fmaf(mk, ge, -(mj * ek));
+      const float w = y3 * (y2 * eh);
+      dm[k] = fmaf(ge, y3, dm[k]);
+      ax[k] = fmaf(y3, gjx, ax[k]);
+      ay[k] = fmaf(y3, gjy, ay[k]);
+      az[k] = fmaf(y3, gjz, az[k]);
+      b[k] = fmaf(y3, mj, b[k]);
+      cx[k] = fmaf(w, ex, cx[k]);
+      cy[k] = fmaf(w, ey, cy[k]);
+      cz[k] = fmaf(w, ez, cz[k]);
+    }
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int k = 0; k < NCH; ++k)
+    r += ax[k] + ay[k] + az[k] + b[k] + cx[k] + cy[k] + cz[k] + dm[k];
+  out[blockIdx.x * kThreads + threadIdx.x] = r;
+  if (threadIdx.x == 0) {
+    const unsigned long long c1 = clock64(), w1 = wall_clock64();
+    unsigned long long *o = stamp + 4 * size_t(blockIdx.x);
+    o[0] = c0;
+    o[1] = c1;
+    o[2] = w0;
+    o[3] = w1;
+  }
+}
+
 template <int NCH>
 __global__ __launch_bounds__(kThreads) void pair_mix(int iters, float seed,
                                                      float *__restrict__ out,
@@ -303,6 +368,10 @@ int main(int argc, char **argv) {
       time_ms([&] { pair_mix<8><<<blocks, kThreads, 0, st>>>(iters / 2, 1.0f, f, stamp); }, st), 8);
   mix("pair_mix_f32, 16 pairs per thread",
       time_ms([&] { pair_mix<16><<<blocks, kThreads, 0, st>>>(iters / 4, 1.0f, f, stamp); }, st), 16);
+  mix("vjp_mix_f32 (split form), 4 pairs per thread",
+      time_ms([&] { vjp_mix<4><<<blocks, kThreads, 0, st>>>(iters, 1.0f, f, stamp); }, st), 4);
+  mix("vjp_mix_f32 (split form), 8 pairs per thread",
+      time_ms([&] { vjp_mix<8><<<blocks, kThreads, 0, st>>>(iters / 2, 1.0f, f, stamp); }, st), 8);
   free(hs);
   CHECK(hipFree(stamp));
   report("cvt_f32_f64+cvt_f64_f32+mul_f64 (per op)",
