@@ -181,6 +181,37 @@ def test_vjp_parity(B, dev, oracle, prec, n):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_accel_parity_mid_size(B, dev, oracle, prec):
+    # N = 17003: the forward's plans with one or four lanes per target, over
+    # several tiles and a ragged tail; every 5th row and the last 64 rows
+    n = 17003
+    say("accel parity mid size", prec, n)
+    pos, _, mass = inputs.uniform_cube(n, 613)
+    rows = np.union1d(np.arange(0, n, 5), np.arange(n - 64, n))
+    ref = oracle.accel_rows(pos, mass, 1.0, 1e-3, rows)
+    got = N(B.nbody_accel(T(pos, dev), T(mass, dev), 1.0, 1e-3, prec))[:, rows]
+    _check_bound(got, ref, _tol.accel_bound(pos, mass, 1.0, 1e-3, prec, rows), prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_vjp_parity_mid_size(B, dev, oracle, prec):
+    # N = 17003: the plans with one or four lanes per target (the small sizes
+    # above all take sixteen), including the FP64 VJP's split form at one
+    # target per lane, over several tiles, diagonal tiles and a ragged tail;
+    # every 5th row and the last 64 rows checked
+    n = 17003
+    say("vjp parity mid size", prec, n)
+    pos, _, mass = inputs.uniform_cube(n, 611)
+    g = inputs.upstream_normal(n, 612)
+    rows = np.union1d(np.arange(0, n, 5), np.arange(n - 64, n))
+    rx, rm = oracle.accel_vjp_rows(pos, mass, g, 1.0, 1e-3, rows)
+    gx, gm = B.nbody_accel_vjp(T(pos, dev), T(mass, dev), T(g, dev), 1.0, 1e-3, prec)
+    bx, bm = _tol.vjp_bound(pos, mass, g, 1.0, 1e-3, prec, rows)
+    _check_bound(N(gx)[:, rows], rx, bx, prec + " dL/dx")
+    assert np.all(np.abs(N(gm)[rows] - rm) <= bm), prec + " dL/dm"
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_vjp_edge_cases(B, dev, oracle, prec):
     say("vjp edge cases", prec)
     # one body: its only pair is the self pair, which adds nothing
