@@ -81,11 +81,12 @@ def test_accel_golden_two_body(B, dev, prec):
 
 
 def test_fp64_pair_within_ulps_across_scales(B, dev):
-    # the FP64 pair (hardware reciprocal square root refined in FP64) against
+    # the FP64 pair (the hardware reciprocal square root's estimate y0, and
+    # m s^-3/2 as m y0^3 times its second-order series correction) against
     # the exact value of G m2 d (|d|^2 + eps^2)^(-3/2), computed with 60-digit
     # decimals, for two bodies over 24 decades of separation and softening:
-    # 3 FMAs for s, the refined 1/sqrt (about 1.2 ulp), two products for
-    # m y^3 and the final product leave at most a few ulp
+    # 3 FMAs for s, the weight (about 2 ulp) and the final product leave at
+    # most a few ulp
     from decimal import Decimal, getcontext
     getcontext().prec = 60
     say("fp64 pair ulps")
