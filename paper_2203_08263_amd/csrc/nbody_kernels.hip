@@ -43,9 +43,18 @@ namespace {
 // of it when row0 = 0, nt = n), sources are all n bodies; output row i (of
 // stride nt) belongs to body row0 + i.
 
+// Largest system the one-launch step serves, per precision (small_system on
+// the host): the step kernel stages all of its sources in LDS at once.
+template <int PREC> constexpr int kSmallMax =
+    PREC == NBODY_FP64 ? 2048 : (PREC == NBODY_MIXED ? 512 : 1024);
+
 // The sums of one lane: its share (tile entries q, q + L, ...) of the sources
 // jbeg .. jend - 1 acting on the R targets of its lane group, without G.
-template <int PREC, int R, int L>
+// With ALL (the one-launch step of a small system) every source is staged in
+// `tile` (kSmallMax<PREC> entries) before the first pair, so the global loads
+// of all tiles are in flight together; the pairs are then visited in the same
+// order as tile by tile, so the sums are bitwise those of the tiled form.
+template <int PREC, int R, int L, bool ALL = false>
 __device__ __forceinline__ void accel_lane_sums(
     int n, int row0, int nt, const double *__restrict__ pos,
     const double *__restrict__ mass, double eps2d, int jbeg, int jend,
@@ -79,17 +88,33 @@ __device__ __forceinline__ void accel_lane_sums(
     ax[r] = ay[r] = az[r] = 0.0;
   }
 
-  for (int jt = jbeg; jt < jend; jt += kThreads) {
-    const int j = jt + tid;
-    const Src<PREC> b = load_src<PREC>(pos, mass, n, j, j < jend);
-    __syncthreads();  // previous tile fully consumed
-    tile[tid] = b;
+  if constexpr (ALL) {
+    constexpr int K = kSmallMax<PREC> / kThreads;
+    Src<PREC> b[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {  // only the tiles the sources reach
+      const int j = jbeg + k * kThreads + tid;
+      if (jbeg + k * kThreads < jend) b[k] = load_src<PREC>(pos, mass, n, j, j < jend);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (jbeg + k * kThreads < jend) tile[k * kThreads + tid] = b[k];
     __syncthreads();
+  }
+  for (int jt = jbeg; jt < jend; jt += kThreads) {
+    if constexpr (!ALL) {
+      const int j = jt + tid;
+      const Src<PREC> b = load_src<PREC>(pos, mass, n, j, j < jend);
+      __syncthreads();  // previous tile fully consumed
+      tile[tid] = b;
+      __syncthreads();
+    }
+    const Src<PREC> *t = ALL ? tile + (jt - jbeg) : tile;
 
     if constexpr (PREC == NBODY_FP64) {
 #pragma unroll 4
       for (int u = 0; u < PER; ++u) {
-        const Src<PREC> s = tile[u * L + q];
+        const Src<PREC> s = t[u * L + q];
 #pragma unroll
         for (int r = 0; r < R; ++r)
           pair_f64(s.x - xi[r], s.y - yi[r], s.z - zi[r], s.m, eps2d, ax[r],
@@ -103,7 +128,7 @@ __device__ __forceinline__ void accel_lane_sums(
         float fx = 0.0f, fy = 0.0f, fz = 0.0f;
         chunk_sum_f32<C, kPairBatch>(
             [&](int u, float &dx, float &dy, float &dz, float &m) {
-              const Src<PREC> s = tile[(u0 + u) * L + q];
+              const Src<PREC> s = t[(u0 + u) * L + q];
               dx = s.x - xi[0];
               dy = s.y - yi[0];
               dz = s.z - zi[0];
@@ -123,7 +148,7 @@ __device__ __forceinline__ void accel_lane_sums(
           float fx = 0.0f, fy = 0.0f, fz = 0.0f;
           chunk_sum_f32<C, kDsBatch>(
               [&](int u, float &dx, float &dy, float &dz, float &m) {
-                const Src<PREC> s = tile[(u0 + u) * L + q];
+                const Src<PREC> s = t[(u0 + u) * L + q];
                 dx = ds_diff(s.x, s.xl, xi[r], xl[r]);
                 dy = ds_diff(s.y, s.yl, yi[r], yl[r]);
                 dz = ds_diff(s.z, s.zl, zi[r], zl[r]);
@@ -145,7 +170,7 @@ __device__ __forceinline__ void accel_lane_sums(
         for (int r = 0; r < R; ++r) fx[r] = fy[r] = fz[r] = 0.0f;
 #pragma unroll
         for (int u = 0; u < C; ++u) {
-          const Src<PREC> s = tile[(u0 + u) * L + q];
+          const Src<PREC> s = t[(u0 + u) * L + q];
 #pragma unroll
           for (int r = 0; r < R; ++r)
             pair_f32(DT(s.x - xi[r]), DT(s.y - yi[r]), DT(s.z - zi[r]), s.m,
@@ -513,12 +538,11 @@ __global__ __launch_bounds__(kBodyThreads) void reduce_kernel(
 // The state update of one (component, body) entry q of [3][n] with its new
 // acceleration a: closing half-kick, checkpoint record, opening half-kick and
 // drift (flags kClose / kOpen).
-__device__ __forceinline__ void update_entry(
-    int n, size_t q, double a, const double *x_in, double *x_out,
-    const double *v_in, double *v_out, double *acc_out, double h, double dt,
-    double *rec, unsigned flags) {
-  const double x = x_in[q];
-  double v = v_in[q];
+// update_entry on the entry's position x and velocity v, already loaded.
+__device__ __forceinline__ void update_entry_xv(
+    int n, size_t q, double a, double x, double v, double *x_out,
+    double *v_out, double *acc_out, double h, double dt, double *rec,
+    unsigned flags) {
   if (flags & kClose) v = v + h * a;
   if (rec) {
     rec[q] = x;
@@ -531,6 +555,14 @@ __device__ __forceinline__ void update_entry(
   }
   v_out[q] = v;
   if (acc_out) acc_out[q] = a;
+}
+
+__device__ __forceinline__ void update_entry(
+    int n, size_t q, double a, const double *x_in, double *x_out,
+    const double *v_in, double *v_out, double *acc_out, double h, double dt,
+    double *rec, unsigned flags) {
+  update_entry_xv(n, q, a, x_in[q], v_in[q], x_out, v_out, acc_out, h, dt, rec,
+                  flags);
 }
 
 __global__ __launch_bounds__(kBodyThreads) void update_kernel(
@@ -556,18 +588,30 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(
     double *__restrict__ x_out, double *acc_out, double *rec, double h,
     double dt, unsigned flags) {
   constexpr int L = 64;
-  __shared__ Src<PREC> tile[kThreads];
+  __shared__ Src<PREC> tile[kSmallMax<PREC>];
+  const int i = blockIdx.x * (kThreads / L) + int(threadIdx.x) / L;
+  const bool upd = threadIdx.x % L == 0 && i < n;
+  // the target's position and velocity, loaded before the force sum so their
+  // latency hides under it (after it, v_in may alias v_out, so the three
+  // components' loads and stores would follow one another)
+  double xs[3] = {0.0, 0.0, 0.0}, vs[3] = {0.0, 0.0, 0.0};
+  if (upd) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xs[c] = x_in[size_t(c) * n + i];
+      vs[c] = v_in[size_t(c) * n + i];
+    }
+  }
   double ax[1], ay[1], az[1];
-  accel_lane_sums<PREC, 1, L>(n, 0, n, x_in, mass, eps2d, 0, n, tile, ax, ay,
-                              az);
+  accel_lane_sums<PREC, 1, L, true>(n, 0, n, x_in, mass, eps2d, 0, n, tile, ax,
+                                    ay, az);
   const double s[3] = {group_sum<L>(ax[0]), group_sum<L>(ay[0]),
                        group_sum<L>(az[0])};
-  const int i = blockIdx.x * (kThreads / L) + int(threadIdx.x) / L;
-  if (threadIdx.x % L == 0 && i < n) {
+  if (upd) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      update_entry(n, size_t(c) * n + i, G * s[c], x_in, x_out, v_in, v_out,
-                   acc_out, h, dt, rec, flags);
+      update_entry_xv(n, size_t(c) * n + i, G * s[c], xs[c], vs[c], x_out,
+                      v_out, acc_out, h, dt, rec, flags);
   }
 }
 
@@ -647,7 +691,7 @@ __global__ __launch_bounds__(kThreads) void diag_block_kernel(
   for (int c = 0; c < kDiag; ++c) red[c][threadIdx.x] = v[c];
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+    if (int(threadIdx.x) < w) {
 #pragma unroll
       for (int c = 0; c < kDiag; ++c)
         red[c][threadIdx.x] = red[c][threadIdx.x] + red[c][threadIdx.x + w];
@@ -868,7 +912,9 @@ hipError_t launch_step_small(int precision, int n, const double *x_in,
                              double *acc_out, double *rec, double h, double dt,
                              unsigned flags, hipStream_t st) {
   const dim3 grid(unsigned((n + kThreads / 64 - 1) / (kThreads / 64)));
+  // the kernel stages all n sources in LDS: n must fit its array
 #define NBODY_STEP_SMALL(PREC_)                                              \
+  if (n > kSmallMax<PREC_>) return hipErrorInvalidValue;                     \
   step_small_kernel<PREC_><<<grid, kThreads, 0, st>>>(                      \
       n, x_in, mass, eps2, G, v_in, v_out, x_out, acc_out, rec, h, dt, flags)
   switch (precision) {
