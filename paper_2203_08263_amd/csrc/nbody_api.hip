@@ -218,7 +218,7 @@ int64_t num_tiles(int64_t n) { return (n + nbody::kThreads - 1) / nbody::kThread
 size_t nf_bytes(nbody::KernelKind kind, int prec, int64_t n, int64_t nt) {
   if (prec != NBODY_MIXED_NF && prec != NBODY_MIXED_NF64) return 0;
   const Plan pl = nbody::make_plan(kind, prec, nt, n);
-  return round_up(nbody::near_far_box_doubles(kind, pl.L, prec == NBODY_MIXED_NF64,
+  return round_up(nbody::near_far_box_doubles(pl, kind, prec == NBODY_MIXED_NF64,
                                               n, nt) *
                   sizeof(double));
 }

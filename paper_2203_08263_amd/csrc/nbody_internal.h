@@ -43,7 +43,7 @@ Plan make_plan_general(KernelKind kind, int precision, int64_t nt, int64_t n);
 // [3][n]), sources all n bodies; plan from make_plan(kind, precision, nt, n).
 // out + s*split_stride + c*nt + i  <-  scale * sum over source split s of the
 // acceleration sum of body row0 + i (without G when scale == 1), c = 0..2.
-// boxes: scratch of near_far_box_doubles(kAccel, pl.L, near64, n, nt) doubles that
+// boxes: scratch of near_far_box_doubles(pl, kAccel, near64, n, nt) doubles that
 // NBODY_MIXED_NF fills with bounding boxes before its kernel (NULL otherwise).
 hipError_t launch_accel(const Plan &pl, int precision, int n, int row0, int nt,
                         const double *pos, const double *mass, double *boxes,
@@ -71,10 +71,11 @@ hipError_t launch_vjp_nf(const Plan &pl, int n, int row0, int nt,
                          double scale, double *ox, double *om, size_t stride,
                          bool near64, hipStream_t st);
 
-// Doubles of bounding-box scratch an NBODY_MIXED_NF launch of `kind` with
-// lanes-per-target L needs for nt targets against n sources.
-size_t near_far_box_doubles(KernelKind kind, int L, bool near64, int64_t n,
-                            int64_t nt);
+// Doubles of near / far scratch (bounding boxes, and the dispatch order of
+// launches large enough to take one) that an NBODY_MIXED_NF / NF64 launch of
+// `kind` with plan pl needs for nt targets against n sources.
+size_t near_far_box_doubles(const Plan &pl, KernelKind kind, bool near64,
+                            int64_t n, int64_t nt);
 
 // Morton (Z-order) sort: keys holds morton_padded(n) entries, boxes
 // ceil(n/256) * 6 doubles, gbox 6; vel / vel_out may both be NULL.

@@ -242,14 +242,14 @@ struct NfBoxes {
 // The wave's and the workgroup's target boxes; a wave with no valid target
 // (tail of the last workgroup) gets an empty box, so every run is far for it.
 template <int L>
-__device__ __forceinline__ void target_boxes(const NfBoxes &bx, int nt,
+__device__ __forceinline__ void target_boxes(const NfBoxes &bx, int nt, int ib,
                                              Box &wave, Box &block) {
   constexpr int GW = 64 / L;
   // wave index, uniform across the wave (scalar registers and branches)
   const int wg = __builtin_amdgcn_readfirstlane(
-      int(blockIdx.x) * (kThreads / 64) + int(threadIdx.x) / 64);
+      ib * (kThreads / 64) + int(threadIdx.x) / 64);
   const bool has = wg * GW < nt;
-  block = read_box(bx.block, blockIdx.x);
+  block = read_box(bx.block, ib);
   wave = read_box(bx.wave, has ? wg : 0);  // box 0 always exists
   const double inf = __builtin_huge_val();
 #pragma unroll
@@ -259,11 +259,141 @@ __device__ __forceinline__ void target_boxes(const NfBoxes &bx, int nt,
   }
 }
 
+// Dispatch order of the near / far launches.  A workgroup's task is one
+// (target block ib, source split s) pair, numbered s * n_ib + ib, and its cost
+// grows with the near runs it holds: in a spatially sorted clustered system
+// the tasks of the dense core are all near and cost up to twice a far one, and
+// when they are dispatched late in grid order they form the launch's tail.
+// nf_load_kernel counts the near (wave, run) pairs of every task from the box
+// arrays, nf_order_kernel sorts the task numbers into three load classes
+// (near share >= 1/4, >= 1/128, the rest; stable, so each class keeps the
+// split-major grid order and its L2 locality), and the kernels take task
+// order[blockIdx.y * n_ib + blockIdx.x], so the costliest tasks start first.
+// Each task writes only its own partial sums, so the order changes when work
+// runs, never what it computes.
+struct NfTask {
+  int ib, s;
+};
+
+__device__ __forceinline__ NfTask nf_task(const int *__restrict__ order) {
+  if (!order) return NfTask{int(blockIdx.x), int(blockIdx.y)};
+  const int t = __builtin_amdgcn_readfirstlane(
+      order[int(blockIdx.y) * int(gridDim.x) + int(blockIdx.x)]);
+  return NfTask{t % int(gridDim.x), t / int(gridDim.x)};
+}
+
+constexpr int kOrderMaxSplits = 64;   // the plans' source split limit
+// Load classes of the dispatch order: near share >= 2^-kOrderShift[k].
+constexpr int kOrderShift[] = {2, 7};
+constexpr int kOrderClasses = sizeof(kOrderShift) / sizeof(int) + 1;
+
+// Near (wave, run) pairs of each task: one workgroup per target block ib
+// (gridDim.x = n_ib), load[s * n_ib + ib] for each source split s.  The test
+// is the kernels' own (a run is near for a wave unless the gap between their
+// boxes exceeds kappa b).
+__global__ __launch_bounds__(kThreads) void nf_load_kernel(
+    int n, int nt, NfBoxes bx, int run, int gw, int jchunk, int nsplit,
+    int *__restrict__ load) {
+  __shared__ int count[kOrderMaxSplits];
+  const int ib = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (tid < nsplit) count[tid] = 0;
+  const Box block = read_box(bx.block, ib);
+  double c[3];
+  const double thr2 = far_frame(block, c);
+  constexpr int W = kThreads / 64;
+  Box wave[W];
+  bool has[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int wg = ib * W + w;
+    has[w] = wg * gw < nt;
+    wave[w] = read_box(bx.wave, has[w] ? wg : 0);
+  }
+  __syncthreads();
+  const int nr = (n + run - 1) / run;
+  for (int r = tid; r < nr; r += kThreads) {
+    const double *sb = bx.run + size_t(r) * 6;
+    double lo[3], hi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = sb[k];
+      hi[k] = sb[3 + k];
+    }
+    int near = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      double gap2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double g =
+            fmax(0.0, fmax(lo[k] - wave[w].hi[k], wave[w].lo[k] - hi[k]));
+        gap2 += g * g;
+      }
+      near += (has[w] && !(gap2 > thr2)) ? 1 : 0;
+    }
+    if (near) atomicAdd(&count[(r * run) / jchunk], near);
+  }
+  __syncthreads();
+  if (tid < nsplit) load[size_t(tid) * gridDim.x + ib] = count[tid];
+}
+
+// One workgroup: order <- the task numbers 0 .. ntask-1 by load class, and
+// within a class in increasing task number (a stable counting sort).  Class
+// k < kOrderClasses - 1 holds the tasks whose near share load / maxload is at
+// least 2^-kOrderShift[k] and not in a lower class; the last class holds the
+// rest, which is most tasks.  Task numbers are split-major, so within a class
+// the resident workgroups share few source splits and the L2 keeps their
+// sources.  Thread t sorts tasks [t * chunk, (t + 1) * chunk).
+__global__ __launch_bounds__(kThreads) void nf_order_kernel(
+    int ntask, int maxload, const int *__restrict__ load,
+    int *__restrict__ order) {
+  constexpr int K = kOrderClasses;
+  __shared__ int cnt[K * kThreads];  // [class][thread], then its exclusive scan
+  __shared__ int part[kThreads];
+  const int tid = threadIdx.x;
+  auto cls = [&](int t) {
+    const int64_t l = min(max(load[t], 0), maxload);
+    int k = 0;
+    while (k < K - 1 && (l << kOrderShift[k]) < int64_t(maxload)) ++k;
+    return k;
+  };
+  const int chunk = (ntask + kThreads - 1) / kThreads;
+  const int t0 = min(ntask, tid * chunk), t1 = min(ntask, t0 + chunk);
+#pragma unroll
+  for (int k = 0; k < K; ++k) cnt[k * kThreads + tid] = 0;
+  for (int t = t0; t < t1; ++t) ++cnt[cls(t) * kThreads + tid];
+  __syncthreads();
+  // exclusive scan of cnt in [class][thread] order: thread t owns entries
+  // [t * K, (t + 1) * K)
+  int local = 0;
+#pragma unroll
+  for (int e = 0; e < K; ++e) local += cnt[tid * K + e];
+  part[tid] = local;
+  for (int off = 1; off < kThreads; off <<= 1) {
+    __syncthreads();
+    const int add = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += add;
+  }
+  __syncthreads();
+  int run = part[tid] - local;
+#pragma unroll
+  for (int e = 0; e < K; ++e) {
+    const int c = cnt[tid * K + e];
+    cnt[tid * K + e] = run;
+    run += c;
+  }
+  __syncthreads();
+  for (int t = t0; t < t1; ++t) order[cnt[cls(t) * kThreads + tid]++] = t;
+}
+
 template <int L, bool NEAR64>
 __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
     int n, int row0, int nt, const double *__restrict__ pos,
-    const double *__restrict__ mass, NfBoxes bx, double eps2d, double scale,
-    int jchunk, double *__restrict__ out, size_t split_stride) {
+    const double *__restrict__ mass, NfBoxes bx, const int *__restrict__ order,
+    double eps2d, double scale, int jchunk, double *__restrict__ out,
+    size_t split_stride) {
   constexpr int G = kThreads / L;
   constexpr int PER = kThreads / L;
   constexpr int C = nf_run(kAccel, L, NEAR64) / L;  // sources per lane and run
@@ -275,8 +405,9 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
 
   const int tid = threadIdx.x;
   const int g = tid / L, q = tid % L;
-  const int i = blockIdx.x * G + g;
-  const int jbeg = blockIdx.y * jchunk;
+  const NfTask task = nf_task(order);
+  const int i = task.ib * G + g;
+  const int jbeg = task.s * jchunk;
   const int jend = min(n, jbeg + jchunk);
   const bool ok = i < nt;
   const int gi = row0 + i;
@@ -284,7 +415,7 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
   const double yi = ok ? pos[n + gi] : 0.0;
   const double zi = ok ? pos[2 * n + gi] : 0.0;
   Box wave, block;
-  target_boxes<L>(bx, nt, wave, block);
+  target_boxes<L>(bx, nt, task.ib, wave, block);
   double c[3];
   const double thr2 = far_frame(block, c);
   const float xr = float(xi - c[0]);
@@ -386,7 +517,7 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
     }
   }
 
-  double *o = out + size_t(blockIdx.y) * split_stride;
+  double *o = out + size_t(task.s) * split_stride;
   const double sx = group_sum<L>(ax);
   const double sy = group_sum<L>(ay);
   const double sz = group_sum<L>(az);
@@ -401,8 +532,8 @@ template <int L, bool NEAR64>
 __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
     int n, int row0, int nt, const double *__restrict__ pos,
     const double *__restrict__ mass, const double *__restrict__ gacc,
-    NfBoxes bx, double eps2d, double scale, int jchunk,
-    double *__restrict__ out_x, double *__restrict__ out_m,
+    NfBoxes bx, const int *__restrict__ order, double eps2d, double scale,
+    int jchunk, double *__restrict__ out_x, double *__restrict__ out_m,
     size_t split_stride) {
   constexpr int G = kThreads / L;
   constexpr int PER = kThreads / L;
@@ -415,8 +546,9 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
 
   const int tid = threadIdx.x;
   const int g = tid / L, q = tid % L;
-  const int k = blockIdx.x * G + g;
-  const int jbeg = blockIdx.y * jchunk;
+  const NfTask task = nf_task(order);
+  const int k = task.ib * G + g;
+  const int jbeg = task.s * jchunk;
   const int jend = min(n, jbeg + jchunk);
   const bool ok = k < nt;
   const int gk = row0 + k;
@@ -432,7 +564,7 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
   const float gky = float(gky64);
   const float gkz = float(gkz64);
   Box wave, block;
-  target_boxes<L>(bx, nt, wave, block);
+  target_boxes<L>(bx, nt, task.ib, wave, block);
   double c[3];
   const double thr2 = far_frame(block, c);
   const float xr = float(xk - c[0]);
@@ -503,7 +635,7 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
     }
     // Tiles that hold some of this workgroup's own targets: the FP32 near
     // runs drop their self pairs (vjp_pair_split); far runs never hold one.
-    const int kblk = row0 + blockIdx.x * G;
+    const int kblk = row0 + task.ib * G;
     const bool diag = jt < kblk + G && jt + kThreads > kblk;
     auto tile_pass = [&](auto diag_tag) {
       constexpr bool D = decltype(diag_tag)::value;
@@ -550,8 +682,8 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
       tile_pass(std::false_type{});
   }
 
-  double *ox = out_x + size_t(blockIdx.y) * split_stride;
-  double *om = out_m + size_t(blockIdx.y) * split_stride;
+  double *ox = out_x + size_t(task.s) * split_stride;
+  double *om = out_m + size_t(task.s) * split_stride;
   double tx = group_sum<L>(sx);
   double ty = group_sum<L>(sy);
   double tz = group_sum<L>(sz);
@@ -713,54 +845,88 @@ __global__ __launch_bounds__(kBodyThreadsSort) void morton_gather_kernel(
   mass_out[r] = mass[src];
 }
 
-// Layout (in doubles) of the near / far box area of one all-pairs launch:
-// run boxes over the n sources, then wave and workgroup boxes over the nt
-// targets.
+// Launches with fewer pairs keep the grid order: the two ordering launches
+// cost a few microseconds, which only pays back on a launch of a millisecond
+// or more (measured on MI355X, clustered system in Morton order: -4 % forward
+// and -2.5 % VJP time at N = 262144).
+constexpr int64_t kNfOrderMinPairs = int64_t(1) << 32;
+
+bool nf_ordered(const Plan &pl, int64_t n, int64_t nt) {
+  return nt * n >= kNfOrderMinPairs && pl.sj <= kOrderMaxSplits;
+}
+
+// Layout (in doubles) of the near / far scratch of one all-pairs launch: run
+// boxes over the n sources, wave and workgroup boxes over the nt targets,
+// then (ordered launches) the task loads and the dispatch order, n_ib * sj
+// ints each.
 struct NfLayout {
   int run, gw, gb;
-  size_t off_wave, off_block, total;
+  bool ordered;
+  int ntask;
+  size_t off_wave, off_block, off_load, off_order, total;
 };
 
-NfLayout nf_layout(KernelKind kind, int L, bool near64, int64_t n,
+NfLayout nf_layout(const Plan &pl, KernelKind kind, bool near64, int64_t n,
                    int64_t nt) {
   NfLayout l;
-  l.run = nf_run(kind, L, near64);
-  l.gw = 64 / L;
-  l.gb = kThreads / L;
+  l.run = nf_run(kind, pl.L, near64);
+  l.gw = 64 / pl.L;
+  l.gb = kThreads / pl.L;
+  l.ordered = nf_ordered(pl, n, nt);
+  l.ntask = int(pl.n_ib * pl.sj);
   const size_t nr = size_t((n + l.run - 1) / l.run);
   const size_t nw = size_t((nt + l.gw - 1) / l.gw);
   const size_t nb = size_t((nt + l.gb - 1) / l.gb);
+  const size_t ints = l.ordered ? size_t(l.ntask + 1) / 2 : 0;  // in doubles
   l.off_wave = nr * 6;
   l.off_block = l.off_wave + nw * 6;
-  l.total = l.off_block + nb * 6;
+  l.off_load = l.off_block + nb * 6;
+  l.off_order = l.off_load + ints;
+  l.total = l.off_order + ints;
   return l;
 }
 
-// Fill the box area for a launch over targets row0 .. row0 + nt - 1: one
+// Fill the box area for a launch over targets row0 .. row0 + nt - 1 (one
 // pass when the targets are all n bodies, otherwise one over the sources and
-// one over the target rows.
-hipError_t launch_nf_boxes(KernelKind kind, int L, bool near64, int n,
+// one over the target rows), then, for an ordered launch, the task loads and
+// the dispatch order; order is left NULL (grid order) otherwise.
+hipError_t launch_nf_boxes(const Plan &pl, KernelKind kind, bool near64, int n,
                            int row0, int nt, const double *pos, double *area,
-                           NfBoxes &bx, hipStream_t st) {
-  const NfLayout l = nf_layout(kind, L, near64, n, nt);
+                           NfBoxes &bx, const int *&order, hipStream_t st) {
+  const NfLayout l = nf_layout(pl, kind, near64, n, nt);
   double *rb = area, *wb = area + l.off_wave, *bb = area + l.off_block;
   bx.run = rb;
   bx.wave = wb;
   bx.block = bb;
+  order = nullptr;
   const unsigned sblocks = unsigned((n + kThreads - 1) / kThreads);
   if (row0 == 0 && nt == n) {
     group_box_kernel<<<sblocks, kThreads, 0, st>>>(n, 0, n, pos, l.run, rb, l.gw,
                                                    wb, l.gb, bb);
-    return hipGetLastError();
+  } else {
+    group_box_kernel<<<sblocks, kThreads, 0, st>>>(n, 0, n, pos, l.run, rb, 0,
+                                                   nullptr, 0, nullptr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned tblocks = unsigned((nt + kThreads - 1) / kThreads);
+    group_box_kernel<<<tblocks, kThreads, 0, st>>>(n, row0, nt, pos, l.gw, wb,
+                                                   l.gb, bb, 0, nullptr);
   }
-  group_box_kernel<<<sblocks, kThreads, 0, st>>>(n, 0, n, pos, l.run, rb, 0,
-                                                 nullptr, 0, nullptr);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !l.ordered) return e;
+  int *load = reinterpret_cast<int *>(area + l.off_load);
+  int *ord = reinterpret_cast<int *>(area + l.off_order);
+  const int jc = int(pl.jchunk), sj = int(pl.sj);
+  nf_load_kernel<<<unsigned(pl.n_ib), kThreads, 0, st>>>(n, nt, bx, l.run, l.gw,
+                                                         jc, sj, load);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const unsigned tblocks = unsigned((nt + kThreads - 1) / kThreads);
-  group_box_kernel<<<tblocks, kThreads, 0, st>>>(n, row0, nt, pos, l.gw, wb,
-                                                 l.gb, bb, 0, nullptr);
-  return hipGetLastError();
+  // (kThreads / 64) waves per workgroup, jchunk / run runs per split
+  const int maxload = (kThreads / 64) * ((jc + l.run - 1) / l.run);
+  nf_order_kernel<<<1, kThreads, 0, st>>>(l.ntask, maxload, load, ord);
+  e = hipGetLastError();
+  if (e == hipSuccess) order = ord;
+  return e;
 }
 
 }  // namespace
@@ -772,15 +938,16 @@ hipError_t launch_accel_nf(const Plan &pl, int n, int row0, int nt,
                            hipStream_t st) {
   if (pl.R != 1) return hipErrorInvalidValue;
   NfBoxes bx;
-  const hipError_t e = launch_nf_boxes(kAccel, pl.L, near64, n, row0, nt, pos, boxes,
-                                       bx, st);
+  const int *order;
+  const hipError_t e = launch_nf_boxes(pl, kAccel, near64, n, row0, nt, pos,
+                                       boxes, bx, order, st);
   if (e != hipSuccess) return e;
   const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
   const int jc = int(pl.jchunk);
 #define NBODY_ACCEL_NF(L_, N64_)                                                 \
   accel_nf_kernel<L_, N64_><<<grid, kThreads, 0, st>>>(n, row0, nt, pos, mass,   \
-                                                       bx, eps2, scale, jc, out, \
-                                                       stride)
+                                                       bx, order, eps2, scale,   \
+                                                       jc, out, stride)
   if (pl.L == 1) { if (near64) NBODY_ACCEL_NF(1, true); else NBODY_ACCEL_NF(1, false); }
   else if (pl.L == 4) { if (near64) NBODY_ACCEL_NF(4, true); else NBODY_ACCEL_NF(4, false); }
   else if (pl.L == 16) { if (near64) NBODY_ACCEL_NF(16, true); else NBODY_ACCEL_NF(16, false); }
@@ -796,15 +963,16 @@ hipError_t launch_vjp_nf(const Plan &pl, int n, int row0, int nt,
                          bool near64, hipStream_t st) {
   if (pl.R != 1) return hipErrorInvalidValue;
   NfBoxes bx;
-  const hipError_t e = launch_nf_boxes(kVjp, pl.L, near64, n, row0, nt, pos, boxes,
-                                       bx, st);
+  const int *order;
+  const hipError_t e = launch_nf_boxes(pl, kVjp, near64, n, row0, nt, pos,
+                                       boxes, bx, order, st);
   if (e != hipSuccess) return e;
   const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
   const int jc = int(pl.jchunk);
 #define NBODY_VJP_NF(L_, N64_)                                                   \
   vjp_nf_kernel<L_, N64_><<<grid, kThreads, 0, st>>>(n, row0, nt, pos, mass,     \
-                                                     gacc, bx, eps2, scale, jc,  \
-                                                     ox, om, stride)
+                                                     gacc, bx, order, eps2,      \
+                                                     scale, jc, ox, om, stride)
   if (pl.L == 1) { if (near64) NBODY_VJP_NF(1, true); else NBODY_VJP_NF(1, false); }
   else if (pl.L == 4) { if (near64) NBODY_VJP_NF(4, true); else NBODY_VJP_NF(4, false); }
   else if (pl.L == 16) { if (near64) NBODY_VJP_NF(16, true); else NBODY_VJP_NF(16, false); }
@@ -813,9 +981,9 @@ hipError_t launch_vjp_nf(const Plan &pl, int n, int row0, int nt,
   return hipGetLastError();
 }
 
-size_t near_far_box_doubles(KernelKind kind, int L, bool near64, int64_t n,
-                            int64_t nt) {
-  return nf_layout(kind, L, near64, n, nt).total;
+size_t near_far_box_doubles(const Plan &pl, KernelKind kind, bool near64,
+                            int64_t n, int64_t nt) {
+  return nf_layout(pl, kind, near64, n, nt).total;
 }
 
 int64_t morton_padded(int64_t n) {

@@ -248,6 +248,54 @@ def test_plummer262144_sorted_share(B, dev, oracle, prec):
     assert np.all(np.abs(gm - rm) <= bm), "dL/dm"
 
 
+@pytest.mark.parametrize("prec", ["mixed_nf", "mixed_nf64"])
+def test_ordered_dispatch_runs_every_task(B, dev, oracle, prec):
+    # Launches of 2^32 pairs or more run their workgroups in an order sorted by
+    # near-run load, computed in the workspace.  A clustered system in Morton
+    # order (tasks of very different loads), n ragged: with the workspace
+    # filled with NaN, then with zeros, every output is finite and the two
+    # results agree bitwise (a task left out, or read from stale scratch,
+    # would show), and sampled rows meet the mode's bound against the oracle.
+    n = 70001
+    say(prec, "ordered dispatch", n)
+    pos, _, mass = inputs.plummer(n, 1900, a=0.1)
+    o = oracle.morton_order(pos)
+    pos, mass = pos[:, o].copy(), mass[o].copy()
+    g = inputs.upstream_normal(n, 1901)
+    P, M, Gt = T(pos, dev), T(mass, dev), T(g, dev)
+    r0, rc = 1000, 65536                 # rows: 65536 * 70001 > 2^32 pairs
+    calls = {
+        "accel": (B.NBODY_OP_ACCEL, lambda ws: [B.nbody_accel(
+            P, M, 1.0, 1e-3, prec, workspace=ws)]),
+        "vjp": (B.NBODY_OP_VJP, lambda ws: list(B.nbody_accel_vjp(
+            P, M, Gt, 1.0, 1e-3, prec, workspace=ws))),
+        "rows": (None, lambda ws: [B.nbody_accel_rows(
+            P, M, r0, rc, 1.0, 1e-3, prec, workspace=ws)]),
+    }
+    got = {}
+    for name, (op, fn) in calls.items():
+        nb = (B.nbody_workspace_bytes(op, n, 0, 1, prec) if op is not None else
+              B.nbody_rows_workspace_bytes(B.NBODY_OP_ACCEL, n, rc, prec))
+        outs = []
+        for fill in (float("nan"), 0.0):
+            ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=dev).fill_(fill)
+            outs.append([N(t) for t in fn(ws.view(torch.uint8))])
+        for a, b in zip(*outs):
+            assert np.all(np.isfinite(a)), name
+            assert np.array_equal(a, b), name
+        got[name] = outs[0]
+    rows = inputs.subset_rows(n, 256, 1902)
+    _check_bound(got["accel"][0][:, rows], oracle.accel_rows(pos, mass, 1.0, 1e-3, rows),
+                 _tol.accel_bound(pos, mass, 1.0, 1e-3, prec, rows), "accel")
+    rx, rm = oracle.accel_vjp_rows(pos, mass, g, 1.0, 1e-3, rows)
+    bx, bm = _tol.vjp_bound(pos, mass, g, 1.0, 1e-3, prec, rows)
+    _check_bound(got["vjp"][0][:, rows], rx, bx, "dL/dx")
+    assert np.all(np.abs(got["vjp"][1][rows] - rm) <= bm), "dL/dm"
+    sub = rows[(rows >= r0) & (rows < r0 + rc)]
+    _check_bound(got["rows"][0][:, sub - r0], oracle.accel_rows(pos, mass, 1.0, 1e-3, sub),
+                 _tol.accel_bound(pos, mass, 1.0, 1e-3, prec, sub), "rows")
+
+
 # ----------------------------------------------------- the accuracy targets --
 
 @pytest.mark.parametrize("name,k", [("cube16384", None), ("plummer65536", 4096),
