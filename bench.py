@@ -76,13 +76,13 @@ KERNEL_KIND = {"accel": "accel_kernel", "vjp": "vjp_kernel"}
 # kernel sources it was taken on (first 16 hex digits of their SHA-256) and
 # is reported as null for any other source.
 MEASURED_TRAFFIC = {
-    # profiles/vjp_nf_kernel_plummer262144_counters.md: 203.8 MB fetched +
+    # profiles/vjp_nf_kernel_plummer262144_counters.md: 487.9 MB fetched +
     # 67.1 MB written by the second vjp_nf_kernel launch
-    ("vjp", "mixed_nf", 262144): {"bytes": 270944472, "src_sha256": "f09c9081e7d456d2"},
-    # same file: 74.7 MB + 50.3 MB, accel_nf_kernel
-    ("accel", "mixed_nf", 262144): {"bytes": 125012198, "src_sha256": "f09c9081e7d456d2"},
+    ("vjp", "mixed_nf", 262144): {"bytes": 555023176, "src_sha256": "212810d1d490b40b"},
+    # same file: 219.3 MB + 50.3 MB, accel_nf_kernel
+    ("accel", "mixed_nf", 262144): {"bytes": 269583261, "src_sha256": "212810d1d490b40b"},
     # profiles/accel_kernel_plummer65536_mixed.md: 16.8 MB + 50.3 MB
-    ("accel", "mixed", 65536): {"bytes": 67167524, "src_sha256": "f09c9081e7d456d2"},
+    ("accel", "mixed", 65536): {"bytes": 67167492, "src_sha256": "212810d1d490b40b"},
 }
 KERNEL_SRC = [os.path.join(ROOT, "paper_2203_08263_amd", "csrc", f)
               for f in ("nbody_kernels.hip", "nbody_nearfar.hip", "nbody_device.h")]
@@ -209,7 +209,8 @@ def roofline(torch, fn, n, kind, p, launches):
     (HIP events on the stream the call launches on, after a clock ramp), and
     its position against the vector peak of its arithmetic type.  A call is
     the all-pairs kernel plus the O(N) split reduction (and, for the near /
-    far modes, the O(N) bounding-box pass)."""
+    far modes, the O(N) bounding-box pass and, at 2^32 pairs or more, the
+    dispatch-order pass)."""
     warm(torch, fn)
     ms = event_ms(torch, fn, launches)
     flops = FLOPS_PER_PAIR[kind] * float(n) * n
