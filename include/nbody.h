@@ -213,8 +213,8 @@ int nbody_accel(int64_t n, const double *pos, const double *mass, double *acc,
  * Errors: as nbody_accel; WORKSPACE_TOO_SMALL, before anything is enqueued,
  * when nbody_workspace_bytes(NBODY_OP_ACCEL, n, 0, 1, precision) exceeds
  * NBODY_NOALLOC_SCRATCH_BYTES.  Every n below 932068 fits for NBODY_MIXED,
- * NBODY_MIXED_D64 and NBODY_MIXED_DS, below 680875 for NBODY_MIXED_NF, below
- * 14510017 for NBODY_MIXED_NF64 and below 65025 for NBODY_FP64 (larger n
+ * NBODY_MIXED_D64 and NBODY_MIXED_DS, below 681198 for NBODY_MIXED_NF, below
+ * 14658561 for NBODY_MIXED_NF64 and below 65025 for NBODY_FP64 (larger n
  * only where that workspace happens to fit).  UNSUPPORTED for a device index
  * of 64 or more. */
 #define NBODY_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)

@@ -287,13 +287,22 @@ constexpr int kOrderMaxSplits = 64;   // the plans' source split limit
 constexpr int kOrderShift[] = {2, 7};
 constexpr int kOrderClasses = sizeof(kOrderShift) / sizeof(int) + 1;
 
-// Near (wave, run) pairs of each task: one workgroup per target block ib
-// (gridDim.x = n_ib), load[s * n_ib + ib] for each source split s.  The test
-// is the kernels' own (a run is near for a wave unless the gap between their
-// boxes exceeds kappa b).
+// Load class of a task with `load` of at most `maxload` near (wave, run)
+// pairs: the first k with load / maxload >= 2^-kOrderShift[k], else the last.
+__device__ __forceinline__ int order_class(int load, int maxload) {
+  const int64_t l = min(max(load, 0), maxload);
+  int k = 0;
+  while (k < kOrderClasses - 1 && (l << kOrderShift[k]) < int64_t(maxload)) ++k;
+  return k;
+}
+
+// Near (wave, run) pairs of each task, as its load class: one workgroup per
+// target block ib (gridDim.x = n_ib), cls[s * n_ib + ib] for each source
+// split s.  The test is the kernels' own (a run is near for a wave unless the
+// gap between their boxes exceeds kappa b).
 __global__ __launch_bounds__(kThreads) void nf_load_kernel(
     int n, int nt, NfBoxes bx, int run, int gw, int jchunk, int nsplit,
-    int *__restrict__ load) {
+    int maxload, unsigned char *__restrict__ cls) {
   __shared__ int count[kOrderMaxSplits];
   const int ib = blockIdx.x;
   const int tid = threadIdx.x;
@@ -335,34 +344,36 @@ __global__ __launch_bounds__(kThreads) void nf_load_kernel(
     if (near) atomicAdd(&count[(r * run) / jchunk], near);
   }
   __syncthreads();
-  if (tid < nsplit) load[size_t(tid) * gridDim.x + ib] = count[tid];
+  if (tid < nsplit)
+    cls[size_t(tid) * gridDim.x + ib] =
+        static_cast<unsigned char>(order_class(count[tid], maxload));
 }
 
-// One workgroup: order <- the task numbers 0 .. ntask-1 by load class, and
-// within a class in increasing task number (a stable counting sort).  Class
-// k < kOrderClasses - 1 holds the tasks whose near share load / maxload is at
-// least 2^-kOrderShift[k] and not in a lower class; the last class holds the
-// rest, which is most tasks.  Task numbers are split-major, so within a class
-// the resident workgroups share few source splits and the L2 keeps their
-// sources.  Thread t sorts tasks [t * chunk, (t + 1) * chunk).
+// One workgroup: order <- the task numbers 0 .. ntask-1 by load class (class
+// 0 first), and within a class in increasing task number (a stable counting
+// sort).  Task numbers are split-major, so within a class the resident
+// workgroups share few source splits and the L2 keeps their sources.  The
+// classes are staged in LDS when they fit (kOrderLdsTasks), read from global
+// memory otherwise; thread t sorts tasks [t * chunk, (t + 1) * chunk).
+constexpr int kOrderLdsTasks = 16384;
+
 __global__ __launch_bounds__(kThreads) void nf_order_kernel(
-    int ntask, int maxload, const int *__restrict__ load,
-    int *__restrict__ order) {
+    int ntask, const unsigned char *__restrict__ cls, int *__restrict__ order) {
   constexpr int K = kOrderClasses;
   __shared__ int cnt[K * kThreads];  // [class][thread], then its exclusive scan
   __shared__ int part[kThreads];
+  __shared__ unsigned char lcls[kOrderLdsTasks];
   const int tid = threadIdx.x;
-  auto cls = [&](int t) {
-    const int64_t l = min(max(load[t], 0), maxload);
-    int k = 0;
-    while (k < K - 1 && (l << kOrderShift[k]) < int64_t(maxload)) ++k;
-    return k;
-  };
+  const bool staged = ntask <= kOrderLdsTasks;  // uniform
+  if (staged)
+    for (int t = tid; t < ntask; t += kThreads) lcls[t] = cls[t];
+  auto cl = [&](int t) { return int(staged ? lcls[t] : cls[t]); };
   const int chunk = (ntask + kThreads - 1) / kThreads;
   const int t0 = min(ntask, tid * chunk), t1 = min(ntask, t0 + chunk);
 #pragma unroll
   for (int k = 0; k < K; ++k) cnt[k * kThreads + tid] = 0;
-  for (int t = t0; t < t1; ++t) ++cnt[cls(t) * kThreads + tid];
+  __syncthreads();
+  for (int t = t0; t < t1; ++t) ++cnt[cl(t) * kThreads + tid];
   __syncthreads();
   // exclusive scan of cnt in [class][thread] order: thread t owns entries
   // [t * K, (t + 1) * K)
@@ -385,7 +396,7 @@ __global__ __launch_bounds__(kThreads) void nf_order_kernel(
     run += c;
   }
   __syncthreads();
-  for (int t = t0; t < t1; ++t) order[cnt[cls(t) * kThreads + tid]++] = t;
+  for (int t = t0; t < t1; ++t) order[cnt[cl(t) * kThreads + tid]++] = t;
 }
 
 template <int L, bool NEAR64>
@@ -857,8 +868,8 @@ bool nf_ordered(const Plan &pl, int64_t n, int64_t nt) {
 
 // Layout (in doubles) of the near / far scratch of one all-pairs launch: run
 // boxes over the n sources, wave and workgroup boxes over the nt targets,
-// then (ordered launches) the task loads and the dispatch order, n_ib * sj
-// ints each.
+// then (ordered launches) the tasks' load classes (n_ib * sj bytes) and the
+// dispatch order (n_ib * sj ints).
 struct NfLayout {
   int run, gw, gb;
   bool ordered;
@@ -877,11 +888,13 @@ NfLayout nf_layout(const Plan &pl, KernelKind kind, bool near64, int64_t n,
   const size_t nr = size_t((n + l.run - 1) / l.run);
   const size_t nw = size_t((nt + l.gw - 1) / l.gw);
   const size_t nb = size_t((nt + l.gb - 1) / l.gb);
-  const size_t ints = l.ordered ? size_t(l.ntask + 1) / 2 : 0;  // in doubles
+  // in doubles
+  const size_t bytes = l.ordered ? size_t(l.ntask + 7) / 8 : 0;
+  const size_t ints = l.ordered ? size_t(l.ntask + 1) / 2 : 0;
   l.off_wave = nr * 6;
   l.off_block = l.off_wave + nw * 6;
   l.off_load = l.off_block + nb * 6;
-  l.off_order = l.off_load + ints;
+  l.off_order = l.off_load + bytes;
   l.total = l.off_order + ints;
   return l;
 }
@@ -914,16 +927,16 @@ hipError_t launch_nf_boxes(const Plan &pl, KernelKind kind, bool near64, int n,
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !l.ordered) return e;
-  int *load = reinterpret_cast<int *>(area + l.off_load);
+  auto *cls = reinterpret_cast<unsigned char *>(area + l.off_load);
   int *ord = reinterpret_cast<int *>(area + l.off_order);
   const int jc = int(pl.jchunk), sj = int(pl.sj);
-  nf_load_kernel<<<unsigned(pl.n_ib), kThreads, 0, st>>>(n, nt, bx, l.run, l.gw,
-                                                         jc, sj, load);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
   // (kThreads / 64) waves per workgroup, jchunk / run runs per split
   const int maxload = (kThreads / 64) * ((jc + l.run - 1) / l.run);
-  nf_order_kernel<<<1, kThreads, 0, st>>>(l.ntask, maxload, load, ord);
+  nf_load_kernel<<<unsigned(pl.n_ib), kThreads, 0, st>>>(n, nt, bx, l.run, l.gw,
+                                                         jc, sj, maxload, cls);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  nf_order_kernel<<<1, kThreads, 0, st>>>(l.ntask, cls, ord);
   e = hipGetLastError();
   if (e == hipSuccess) order = ord;
   return e;

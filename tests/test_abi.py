@@ -177,7 +177,7 @@ def test_accel_noalloc_rejects_invalid_arguments(B, kw, msg):
 # first size over it for each precision, and the largest workspaces of the
 # FP32-pair modes (2 source splits of just under 2^21 bodies).
 @pytest.mark.parametrize("n,prec", [(65025, 0), (262144, 0), (932068, 1), (2096891, 1),
-                                    (932068, 2), (680875, 3), (14510017, 4),
+                                    (932068, 2), (681198, 3), (14658561, 4),
                                     (932068, 5)])
 def test_accel_noalloc_rejects_sizes_beyond_its_scratch(B, n, prec):
     need = B.nbody_workspace_bytes(B.NBODY_OP_ACCEL, n, 0, 1, prec)
@@ -193,7 +193,7 @@ def test_accel_noalloc_limits_match_the_header(B):
     txt = open(HEADER).read()
     assert re.search(r"NBODY_NOALLOC_SCRATCH_BYTES \(\(size_t\)64 << 20\)", txt)
     assert lim == 64 << 20
-    first = {0: 65025, 1: 932068, 2: 932068, 3: 680875, 4: 14510017, 5: 932068}
+    first = {0: 65025, 1: 932068, 2: 932068, 3: 681198, 4: 14658561, 5: 932068}
     for prec, nf in first.items():
         assert B.nbody_workspace_bytes(B.NBODY_OP_ACCEL, nf, 0, 1, prec) > lim
         grid = sorted(set(list(range(1, min(nf, 70000), 97)) + [nf - 1, nf - 2, nf - 255]
