@@ -296,6 +296,41 @@ def test_ordered_dispatch_runs_every_task(B, dev, oracle, prec):
                  _tol.accel_bound(pos, mass, 1.0, 1e-3, prec, sub), "rows")
 
 
+@pytest.mark.parametrize("prec", ["mixed_nf", "mixed_nf64"])
+def test_ordered_dispatch_in_step_and_adjoint(B, dev, oracle, prec):
+    # The step loop and the adjoint of a system with ordered launches (n = 65536,
+    # 2^32 pairs) run the same ordered kernels: the acceleration a step leaves
+    # equals nbody_accel at the new positions bitwise; the adjoint, with its
+    # workspace filled with NaN and then with zeros, is finite and the same
+    # bitwise.
+    n, S, K = 65536, 2, 1
+    say(prec, "ordered step + adjoint", n)
+    pos, vel, mass = inputs.plummer(n, 1950, a=0.1)
+    o = oracle.morton_order(pos)
+    pos, vel, mass = pos[:, o].copy(), vel[:, o].copy(), mass[o].copy()
+    P, V, M = T(pos, dev), T(vel, dev), T(mass, dev)
+    A = torch.empty_like(P)
+    ck = torch.empty(B.nbody_checkpoint_bytes(n, S, K) // 8, dtype=torch.float64,
+                     device=dev)
+    nb = B.nbody_workspace_bytes(B.NBODY_OP_STEP, n, S, K, prec)
+    ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=dev).fill_(float("nan"))
+    B.nbody_step(P, V, A, M, 1.0, 1e-3, 1e-3, S, prec, ckpt=ck, ckpt_every=K,
+                 workspace=ws.view(torch.uint8))
+    assert torch.equal(A, B.nbody_accel(P, M, 1.0, 1e-3, prec))
+    gxT = inputs.upstream_normal(n, 1951)
+    gvT = inputs.upstream_normal(n, 1952)
+    nb = B.nbody_workspace_bytes(B.NBODY_OP_STEP_ADJOINT, n, S, K, prec)
+    outs = []
+    for fill in (float("nan"), 0.0):
+        ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=dev).fill_(fill)
+        r = B.nbody_step_adjoint(ck, M, T(gxT, dev), T(gvT, dev), 1.0, 1e-3, 1e-3,
+                                 S, K, prec, workspace=ws.view(torch.uint8))
+        outs.append([N(t) for t in r])
+    for a, b in zip(*outs):
+        assert np.all(np.isfinite(a))
+        assert np.array_equal(a, b)
+
+
 # ----------------------------------------------------- the accuracy targets --
 
 @pytest.mark.parametrize("name,k", [("cube16384", None), ("plummer65536", 4096),
