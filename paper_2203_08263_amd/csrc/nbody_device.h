@@ -15,7 +15,7 @@ namespace nbody {
 namespace {
 
 constexpr int kChunk = 32;        // FP32 sources per FP64 flush (forward)
-constexpr int kVjpChunk = 16;     // FP32 sources per FP64 flush (VJP)
+constexpr int kVjpChunk = 32;     // FP32 sources per FP64 flush (VJP)
 constexpr int kPairBatch = 8;     // FP32 pair weights formed ahead of their sums
 constexpr int kDsBatch = 4;       // the same for two-float differences
 constexpr int kBodyThreads = 64;  // threads per workgroup, per-body kernels

@@ -221,12 +221,17 @@ __global__ __launch_bounds__(kThreads) void accel_kernel(
 
 // Resident waves per SIMD the VJP kernels are compiled for.  Left free, the
 // compiler hoists a whole chunk's LDS reads in the FP32-pair kernels and needs
-// up to 106 VGPRs (4 waves); held to 8 waves (64 VGPRs) they lose nothing
+// over 100 VGPRs (4 waves); held to 8 waves (64 VGPRs) they lose nothing
 // and do not spill, except the D64 kernel at L = 16 (77 VGPRs, 6 waves, no
-// spill).  FP64 (78 VGPRs and 6 waves at one target per lane, about 90 and
-// 5 at two) is left to the compiler: the split form spills at 7 or 8.
+// spill) and the mixed kernel at L = 1, which with chunks of 32 sources
+// spills at 8 waves and is held to 7 (72 VGPRs; seven spilled, and still
+// 1.3-1.9 % faster than chunks of 16 at 8 waves; at 6 waves it spills more).
+// FP64 (78 VGPRs and 6 waves at one target per lane, about 90 and 5 at two)
+// is left to the compiler: the split form spills at 7 or 8.
 constexpr int vjp_waves(int prec, int L) {
-  return prec == NBODY_FP64 ? 1 : (prec == NBODY_MIXED_D64 && L == 16 ? 6 : 8);
+  if (prec == NBODY_FP64) return 1;
+  if (prec == NBODY_MIXED_D64 && L == 16) return 6;
+  return prec == NBODY_MIXED && L == 1 ? 7 : 8;
 }
 
 // Rows as in accel_kernel: targets k = row0 .. row0 + nt - 1, sources all n

@@ -53,16 +53,12 @@ constexpr int kNfFarBatch = 4;
 // largest relative error over all 262144 bodies of a clustered Plummer
 // system 1.1e-6 -> 7.2e-7; +4 % at N = 16384, -3 % at N = 262144).
 constexpr int kNf64Chunk = 16;
-// The NBODY_MIXED_NF VJP sums chunks of 32 (the plain FP32-pair VJP: 16,
-// which keeps its L = 1 kernel within 64 VGPRs): half the chunk flushes, the
-// costliest non-pair work of the split-form pair, for runs of 32 sources
-// (slightly more of them near) and a chunk-summation term of the error bound
-// twice as large (32 u32 of each term instead of 16; measured: -1.3 % VJP
-// time at N = 65536, -1.9 % at 262144).
-constexpr int kNfVjpChunk = 32;
+// The NBODY_MIXED_NF64 VJP keeps runs of 16 sources (the other VJPs: 32):
+// its near runs are FP64 pairs, and finer runs leave fewer of them near.
+constexpr int kNf64VjpChunk = 16;
 
 constexpr int nf_chunk(KernelKind kind, bool near64) {
-  if (kind == kVjp) return near64 ? kVjpChunk : kNfVjpChunk;
+  if (kind == kVjp) return near64 ? kNf64VjpChunk : kVjpChunk;
   return near64 ? kNf64Chunk : kChunk;
 }
 

@@ -40,8 +40,7 @@ U32 = 2.0 ** -24
 U64 = 2.0 ** -53
 SAFETY = 2.0
 CHUNK32 = 32
-VJP_CHUNK32 = 16
-NF_VJP_CHUNK32 = 32     # the mixed_nf VJP's chunks
+VJP_CHUNK32 = 32        # mixed_nf64's VJP: 16 (its bound with 32 is looser)
 
 
 # Far runs of the near / far mode: a pair distance above kappa = 1/2 times
@@ -213,7 +212,7 @@ def vjp_bound(pos, mass, gacc, G, eps, precision, rows=None):
     if precision == "fp64":
         u, L = U64, n + 64
     else:
-        u, L = U32, (NF_VJP_CHUNK32 if precision == "mixed_nf" else VJP_CHUNK32)
+        u, L = U32, VJP_CHUNK32
     ax = 4.0 * (40 + L) * u * A[0]
     am = (16 + L) * u * Be
     if precision == "fp64":

@@ -32,10 +32,7 @@ def _direct_vjp(pos, mass, g, G, eps, prec, rows):
     n = mass.size
     xn = np.linalg.norm(pos, axis=0)
     gn = np.linalg.norm(g, axis=0)
-    if prec == "fp64":
-        u, L = _tol.U64, n + 64
-    else:
-        u, L = _tol.U32, (_tol.NF_VJP_CHUNK32 if prec == "mixed_nf" else _tol.VJP_CHUNK32)
+    u, L = (_tol.U64, n + 64) if prec == "fp64" else (_tol.U32, _tol.VJP_CHUNK32)
     bx, bm = [], []
     for k in rows:
         e = pos - pos[:, k:k + 1]
