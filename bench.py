@@ -76,16 +76,19 @@ KERNEL_KIND = {"accel": "accel_kernel", "vjp": "vjp_kernel"}
 # kernel sources it was taken on (first 16 hex digits of their SHA-256) and
 # is reported as null for any other source.
 MEASURED_TRAFFIC = {
-    # profiles/vjp_nf_kernel_plummer262144_counters.md: 465.8 MB fetched +
-    # 67.1 MB written by the second vjp_nf_kernel launch
-    ("vjp", "mixed_nf", 262144): {"bytes": 532878177, "src_sha256": "08b53f98e10fc651"},
+    # profiles/vjp_nf_kernel_plummer262144_counters.md: 547.8 MB fetched +
+    # 134.2 MB written by the second vjp_nf_kernel launch
+    ("vjp", "mixed_nf", 262144): {"bytes": 682059793, "src_sha256": "c64546ee00240845"},
     # same file: 219.4 MB + 50.3 MB, accel_nf_kernel
-    ("accel", "mixed_nf", 262144): {"bytes": 269742057, "src_sha256": "08b53f98e10fc651"},
+    ("accel", "mixed_nf", 262144): {"bytes": 269779253, "src_sha256": "c64546ee00240845"},
     # profiles/accel_kernel_plummer65536_mixed.md: 16.8 MB + 50.3 MB
-    ("accel", "mixed", 65536): {"bytes": 67167460, "src_sha256": "08b53f98e10fc651"},
+    ("accel", "mixed", 65536): {"bytes": 67167364, "src_sha256": "c64546ee00240845"},
 }
+# the kernels and the launch plans (nbody_api.hip), which set the split
+# partials' bytes
 KERNEL_SRC = [os.path.join(ROOT, "paper_2203_08263_amd", "csrc", f)
-              for f in ("nbody_kernels.hip", "nbody_nearfar.hip", "nbody_device.h")]
+              for f in ("nbody_kernels.hip", "nbody_nearfar.hip", "nbody_device.h",
+                        "nbody_api.hip")]
 
 
 def log(*a):

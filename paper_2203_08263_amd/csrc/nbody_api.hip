@@ -87,8 +87,17 @@ Plan make_plan_general(KernelKind kind, int precision, int64_t nt, int64_t n) {
   // near runs are FP64 pairs, and the finer target waves and source runs of
   // L = 4 leave fewer pairs near (measured: +21 % forward at N = 65536, +8 %
   // at 262144, equal at 16384; L = 16 is slower for both near / far modes).
+  // A VJP source split spans at most 64 tiles (sj raised, to at most 64):
+  // shorter workgroups leave a shorter tail when the last round drains
+  // (measured at N = 262144, 16 splits of 64 tiles against 8 of 128: -1.3 to
+  // -1.6 % for the mixed and near / far VJP, -2.1 % for the forward; 32 of 32:
+  // about the same, at twice the partial sums; no change at N = 65536 and
+  // below).  The force keeps its 8192-workgroup shape: more splits would
+  // more than double the partial sums of large systems, which the
+  // allocation-free force call must hold in its fixed static scratch.
   const int64_t target = 8192, max_sj = 64;
   const int64_t ntiles = (n + kThreads - 1) / kThreads;
+  const int64_t max_split_tiles = kind == kVjp ? 64 : ntiles;
   auto shape = [&](int R) {
     Plan p{};
     for (int L : {1, 4, 16}) {
@@ -110,6 +119,7 @@ Plan make_plan_general(KernelKind kind, int precision, int64_t nt, int64_t n) {
     if (precision == NBODY_FP64 && kind == kVjp && p.L == 16) p = shape(2);
   }
   p.sj = std::max<int64_t>(1, std::min({p.sj, ntiles, max_sj}));
+  p.sj = std::min(max_sj, std::max(p.sj, (ntiles + max_split_tiles - 1) / max_split_tiles));
   const int64_t tiles_per_split = (ntiles + p.sj - 1) / p.sj;
   p.jchunk = tiles_per_split * kThreads;
   p.sj = (n + p.jchunk - 1) / p.jchunk;
