@@ -76,13 +76,13 @@ KERNEL_KIND = {"accel": "accel_kernel", "vjp": "vjp_kernel"}
 # kernel sources it was taken on (first 16 hex digits of their SHA-256) and
 # is reported as null for any other source.
 MEASURED_TRAFFIC = {
-    # profiles/vjp_nf_kernel_plummer262144_counters.md: 547.8 MB fetched +
+    # profiles/vjp_nf_kernel_plummer262144_counters.md: 555.5 MB fetched +
     # 134.2 MB written by the second vjp_nf_kernel launch
-    ("vjp", "mixed_nf", 262144): {"bytes": 682059793, "src_sha256": "c64546ee00240845"},
-    # same file: 219.4 MB + 50.3 MB, accel_nf_kernel
-    ("accel", "mixed_nf", 262144): {"bytes": 269779253, "src_sha256": "c64546ee00240845"},
+    ("vjp", "mixed_nf", 262144): {"bytes": 689756951, "src_sha256": "4acd5eafbbdb6683"},
+    # same file: 212.4 MB + 50.3 MB, accel_nf_kernel
+    ("accel", "mixed_nf", 262144): {"bytes": 262737266, "src_sha256": "4acd5eafbbdb6683"},
     # profiles/accel_kernel_plummer65536_mixed.md: 16.8 MB + 50.3 MB
-    ("accel", "mixed", 65536): {"bytes": 67167364, "src_sha256": "c64546ee00240845"},
+    ("accel", "mixed", 65536): {"bytes": 67169539, "src_sha256": "4acd5eafbbdb6683"},
 }
 # the kernels and the launch plans (nbody_api.hip), which set the split
 # partials' bytes

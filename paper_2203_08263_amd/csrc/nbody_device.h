@@ -20,6 +20,24 @@ constexpr int kPairBatch = 8;     // FP32 pair weights formed ahead of their sum
 constexpr int kDsBatch = 4;       // the same for two-float differences
 constexpr int kBodyThreads = 64;  // threads per workgroup, per-body kernels
 
+// Source range [jbeg, jend) of split s.
+__device__ __forceinline__ void split_range(const SplitShape &sp, int s, int n,
+                                            int &jbeg, int &jend) {
+  const bool lng = s < sp.nlong;
+  const int64_t b = lng ? int64_t(s) * sp.llong
+                        : int64_t(sp.nlong) * sp.llong +
+                              int64_t(s - sp.nlong) * sp.lshort;
+  jbeg = int(b < n ? b : n);
+  const int64_t e = b + (lng ? sp.llong : sp.lshort);
+  jend = int(e < n ? e : n);
+}
+
+// The split that holds source j.
+__device__ __forceinline__ int split_of(const SplitShape &sp, int j) {
+  const int64_t edge = int64_t(sp.nlong) * sp.llong;
+  return j < edge ? j / sp.llong : sp.nlong + int((j - edge) / sp.lshort);
+}
+
 // -------------------------------------------------------------- arithmetic --
 
 // 1/sqrt(s) in FP64: the hardware estimate y0 refined by one third-order

@@ -22,7 +22,7 @@ __device__ __forceinline__ float group_sum_f(float v) {
 template <int L>
 __global__ __launch_bounds__(kThreads) void accel_f32_kernel(
     int n, const float *__restrict__ pos, const float *__restrict__ mass,
-    float eps2, float scale, int jchunk, float *__restrict__ out,
+    float eps2, float scale, SplitShape split, float *__restrict__ out,
     size_t split_stride) {
   constexpr int G = kThreads / L;
   constexpr int PER = kThreads / L;
@@ -31,8 +31,8 @@ __global__ __launch_bounds__(kThreads) void accel_f32_kernel(
   const int tid = threadIdx.x;
   const int g = tid / L, q = tid % L;
   const int i = blockIdx.x * G + g;
-  const int jbeg = blockIdx.y * jchunk;
-  const int jend = min(n, jbeg + jchunk);
+  int jbeg, jend;
+  split_range(split, blockIdx.y, n, jbeg, jend);
   const bool ok = i < n;
   const float xi = ok ? pos[i] : 0.0f;
   const float yi = ok ? pos[n + i] : 0.0f;
@@ -114,7 +114,7 @@ hipError_t launch_accel_f32(const Plan &pl, int n, const float *pos,
                             float *out, size_t stride, hipStream_t st) {
   if (pl.R != 1) return hipErrorInvalidValue;
   const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
-  const int jc = int(pl.jchunk);
+  const SplitShape jc = pl.split;
   if (pl.L == 1)
     accel_f32_kernel<1><<<grid, kThreads, 0, st>>>(n, pos, mass, eps2, scale, jc,
                                                    out, stride);

@@ -11,17 +11,24 @@ namespace nbody {
 // Threads per workgroup of every kernel (4 wave64s) and bodies per LDS tile.
 constexpr int kThreads = 256;
 
+// Source ranges of the sj splits of an all-pairs launch: nlong splits of
+// llong bodies, then splits of lshort bodies (both multiples of kThreads),
+// the last one ending at n.  Uniform splits have nlong = sj.
+struct SplitShape {
+  int nlong, llong, lshort;
+};
+
 // Launch plan of one all-pairs kernel: L lanes share each target body and
 // each lane group serves R targets, so a workgroup owns (kThreads/L)*R
-// targets; n_ib target blocks; sj source splits of jchunk bodies (jchunk a
-// multiple of kThreads).  Depends only on (kind, precision, nt, n), so a
-// recomputation reproduces every partial sum bitwise.
+// targets; n_ib target blocks; sj source splits shaped by split.  Depends
+// only on (kind, precision, nt, n), so a recomputation reproduces every
+// partial sum bitwise.
 struct Plan {
   int R;
   int L;
   int64_t n_ib;
   int64_t sj;
-  int64_t jchunk;
+  SplitShape split;
 };
 
 enum KernelKind { kAccel = 0, kVjp = 1, kPotential = 2 };

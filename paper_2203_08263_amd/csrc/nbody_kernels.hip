@@ -3,7 +3,7 @@
 // The all-pairs kernels (acceleration and its VJP) share one shape:
 //  - a workgroup of 256 threads (4 wave64s) owns kThreads*R target bodies,
 //    R per thread, strided by kThreads so every load and store is coalesced;
-//  - blockIdx.y selects a contiguous source range of jchunk bodies, staged
+//  - blockIdx.y selects a contiguous source range (SplitShape), staged
 //    through LDS in tiles of 256 bodies, one body loaded per thread from the
 //    structure-of-arrays FP64 state.  In the mixed modes the staging step is
 //    where positions and masses are rounded to FP32 (the "pack" of the source
@@ -190,14 +190,14 @@ __device__ __forceinline__ void accel_lane_sums(
 template <int PREC, int R, int L>
 __global__ __launch_bounds__(kThreads) void accel_kernel(
     int n, int row0, int nt, const double *__restrict__ pos,
-    const double *__restrict__ mass, double eps2d, double scale, int jchunk,
+    const double *__restrict__ mass, double eps2d, double scale, SplitShape split,
     double *__restrict__ out, size_t split_stride) {
   constexpr int G = kThreads / L;
   __shared__ Src<PREC> tile[kThreads];
   const int g = threadIdx.x / L, q = threadIdx.x % L;
   const int ibase = blockIdx.x * (G * R) + g;
-  const int jbeg = blockIdx.y * jchunk;
-  const int jend = min(n, jbeg + jchunk);
+  int jbeg, jend;
+  split_range(split, blockIdx.y, n, jbeg, jend);
   double ax[R], ay[R], az[R];
   accel_lane_sums<PREC, R, L>(n, row0, nt, pos, mass, eps2d, jbeg, jend, tile,
                               ax, ay, az);
@@ -240,7 +240,7 @@ template <int PREC, int R, int L>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(vjp_waves(PREC, L)))) void vjp_kernel(
     int n, int row0, int nt, const double *__restrict__ pos,
     const double *__restrict__ mass, const double *__restrict__ gacc,
-    double eps2d, double scale, int jchunk, double *__restrict__ out_x,
+    double eps2d, double scale, SplitShape split, double *__restrict__ out_x,
     double *__restrict__ out_m, size_t split_stride) {
   using CT = typename Coord<PREC>::T;
   using DT = typename Coord<PREC>::D;
@@ -253,8 +253,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(vjp_wa
   const int tid = threadIdx.x;
   const int g = tid / L, q = tid % L;
   const int kbase = blockIdx.x * (G * R) + g;
-  const int jbeg = blockIdx.y * jchunk;
-  const int jend = min(n, jbeg + jchunk);
+  int jbeg, jend;
+  split_range(split, blockIdx.y, n, jbeg, jend);
 
   CT xk[R], yk[R], zk[R];
   float xl[R], yl[R], zl[R];  // lo parts (NBODY_MIXED_DS only)
@@ -436,7 +436,7 @@ __device__ __forceinline__ double self_potential_term(T m, T eps2) {
 template <int PREC, int L>
 __global__ __launch_bounds__(kThreads) void potential_kernel(
     int n, const double *__restrict__ pos, const double *__restrict__ mass,
-    double eps2d, int jchunk, double *__restrict__ out) {
+    double eps2d, SplitShape split, double *__restrict__ out) {
   using CT = typename Coord<PREC>::T;
   using DT = typename Coord<PREC>::D;
   constexpr int G = kThreads / L;
@@ -447,8 +447,8 @@ __global__ __launch_bounds__(kThreads) void potential_kernel(
   const int tid = threadIdx.x;
   const int g = tid / L, q = tid % L;
   const int i = blockIdx.x * G + g;
-  const int jbeg = blockIdx.y * jchunk;
-  const int jend = min(n, jbeg + jchunk);
+  int jbeg, jend;
+  split_range(split, blockIdx.y, n, jbeg, jend);
   const bool ok = i < n;
   CT xi, yi, zi;
   float xl = 0.0f, yl = 0.0f, zl = 0.0f;  // lo parts (NBODY_MIXED_DS only)
@@ -736,7 +736,7 @@ hipError_t launch_accel_p(const Plan &pl, int n, int row0, int nt,
                           double scale, double *out, size_t stride,
                           hipStream_t st) {
   const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
-  const int jc = int(pl.jchunk);
+  const SplitShape jc = pl.split;
 #define NBODY_ACCEL_CALL(R_, L_)                                             \
   accel_kernel<PREC, R_, L_><<<grid, kThreads, 0, st>>>(                    \
       n, row0, nt, pos, mass, eps2, scale, jc, out, stride)
@@ -751,7 +751,7 @@ hipError_t launch_vjp_p(const Plan &pl, int n, int row0, int nt,
                         const double *gacc, double eps2, double scale,
                         double *ox, double *om, size_t stride, hipStream_t st) {
   const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
-  const int jc = int(pl.jchunk);
+  const SplitShape jc = pl.split;
 #define NBODY_VJP_CALL(R_, L_)                                               \
   vjp_kernel<PREC, R_, L_><<<grid, kThreads, 0, st>>>(                      \
       n, row0, nt, pos, mass, gacc, eps2, scale, jc, ox, om, stride)
@@ -829,7 +829,7 @@ hipError_t launch_potential(const Plan &pl, int precision, int n,
                             const double *pos, const double *mass, double eps2,
                             double *out, hipStream_t st) {
   const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
-  const int jc = int(pl.jchunk);
+  const SplitShape jc = pl.split;
 #define NBODY_POT(PREC_)                                                      \
   do {                                                                        \
     if (pl.L == 1)                                                            \

@@ -300,13 +300,14 @@ __device__ __forceinline__ int order_class(int load, int maxload) {
   return k;
 }
 
-// Near (wave, run) pairs of each task, as its load class: one workgroup per
-// target block ib (gridDim.x = n_ib), cls[s * n_ib + ib] for each source
-// split s.  The test is the kernels' own (a run is near for a wave unless the
-// gap between their boxes exceeds kappa b).
+// Near (wave, run) pairs of each task, as its load class (against the
+// (wave, run) pairs of its split): one workgroup per target block ib
+// (gridDim.x = n_ib), cls[s * n_ib + ib] for each source split s.  The test
+// is the kernels' own (a run is near for a wave unless the gap between their
+// boxes exceeds kappa b).
 __global__ __launch_bounds__(kThreads) void nf_load_kernel(
-    int n, int nt, NfBoxes bx, int run, int gw, int jchunk, int nsplit,
-    int maxload, unsigned char *__restrict__ cls) {
+    int n, int nt, NfBoxes bx, int run, int gw, SplitShape split, int nsplit,
+    unsigned char *__restrict__ cls) {
   __shared__ int count[kOrderMaxSplits];
   const int ib = blockIdx.x;
   const int tid = threadIdx.x;
@@ -345,12 +346,16 @@ __global__ __launch_bounds__(kThreads) void nf_load_kernel(
       }
       near += (has[w] && !(gap2 > thr2)) ? 1 : 0;
     }
-    if (near) atomicAdd(&count[(r * run) / jchunk], near);
+    if (near) atomicAdd(&count[split_of(split, r * run)], near);
   }
   __syncthreads();
-  if (tid < nsplit)
+  if (tid < nsplit) {
+    int jb, je;
+    split_range(split, tid, n, jb, je);
+    const int maxload = max(1, W * ((je - jb + run - 1) / run));
     cls[size_t(tid) * gridDim.x + ib] =
         static_cast<unsigned char>(order_class(count[tid], maxload));
+  }
 }
 
 // One workgroup: order <- the task numbers 0 .. ntask-1 by load class (class
@@ -407,7 +412,7 @@ template <int L, bool NEAR64>
 __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
     int n, int row0, int nt, const double *__restrict__ pos,
     const double *__restrict__ mass, NfBoxes bx, const int *__restrict__ order,
-    double eps2d, double scale, int jchunk, double *__restrict__ out,
+    double eps2d, double scale, SplitShape split, double *__restrict__ out,
     size_t split_stride) {
   constexpr int G = kThreads / L;
   constexpr int PER = kThreads / L;
@@ -422,8 +427,8 @@ __global__ __launch_bounds__(kThreads) void accel_nf_kernel(
   const int g = tid / L, q = tid % L;
   const NfTask task = nf_task(order);
   const int i = task.ib * G + g;
-  const int jbeg = task.s * jchunk;
-  const int jend = min(n, jbeg + jchunk);
+  int jbeg, jend;
+  split_range(split, task.s, n, jbeg, jend);
   const bool ok = i < nt;
   const int gi = row0 + i;
   const double xi = ok ? pos[gi] : 0.0;
@@ -548,7 +553,7 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
     int n, int row0, int nt, const double *__restrict__ pos,
     const double *__restrict__ mass, const double *__restrict__ gacc,
     NfBoxes bx, const int *__restrict__ order, double eps2d, double scale,
-    int jchunk, double *__restrict__ out_x, double *__restrict__ out_m,
+    SplitShape split, double *__restrict__ out_x, double *__restrict__ out_m,
     size_t split_stride) {
   constexpr int G = kThreads / L;
   constexpr int PER = kThreads / L;
@@ -563,8 +568,8 @@ __global__ __launch_bounds__(kThreads) void vjp_nf_kernel(
   const int g = tid / L, q = tid % L;
   const NfTask task = nf_task(order);
   const int k = task.ib * G + g;
-  const int jbeg = task.s * jchunk;
-  const int jend = min(n, jbeg + jchunk);
+  int jbeg, jend;
+  split_range(split, task.s, n, jbeg, jend);
   const bool ok = k < nt;
   const int gk = row0 + k;
   const double xk = ok ? pos[gk] : 0.0;
@@ -933,11 +938,8 @@ hipError_t launch_nf_boxes(const Plan &pl, KernelKind kind, bool near64, int n,
   if (e != hipSuccess || !l.ordered) return e;
   auto *cls = reinterpret_cast<unsigned char *>(area + l.off_load);
   int *ord = reinterpret_cast<int *>(area + l.off_order);
-  const int jc = int(pl.jchunk), sj = int(pl.sj);
-  // (kThreads / 64) waves per workgroup, jchunk / run runs per split
-  const int maxload = (kThreads / 64) * ((jc + l.run - 1) / l.run);
   nf_load_kernel<<<unsigned(pl.n_ib), kThreads, 0, st>>>(n, nt, bx, l.run, l.gw,
-                                                         jc, sj, maxload, cls);
+                                                         pl.split, int(pl.sj), cls);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   nf_order_kernel<<<1, kThreads, 0, st>>>(l.ntask, cls, ord);
@@ -960,7 +962,7 @@ hipError_t launch_accel_nf(const Plan &pl, int n, int row0, int nt,
                                        boxes, bx, order, st);
   if (e != hipSuccess) return e;
   const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
-  const int jc = int(pl.jchunk);
+  const SplitShape jc = pl.split;
 #define NBODY_ACCEL_NF(L_, N64_)                                                 \
   accel_nf_kernel<L_, N64_><<<grid, kThreads, 0, st>>>(n, row0, nt, pos, mass,   \
                                                        bx, order, eps2, scale,   \
@@ -985,7 +987,7 @@ hipError_t launch_vjp_nf(const Plan &pl, int n, int row0, int nt,
                                        boxes, bx, order, st);
   if (e != hipSuccess) return e;
   const dim3 grid(unsigned(pl.n_ib), unsigned(pl.sj));
-  const int jc = int(pl.jchunk);
+  const SplitShape jc = pl.split;
 #define NBODY_VJP_NF(L_, N64_)                                                   \
   vjp_nf_kernel<L_, N64_><<<grid, kThreads, 0, st>>>(n, row0, nt, pos, mass,     \
                                                      gacc, bx, order, eps2,      \
