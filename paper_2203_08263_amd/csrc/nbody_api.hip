@@ -124,11 +124,12 @@ Plan make_plan_general(KernelKind kind, int precision, int64_t nt, int64_t n) {
   p.sj = (ntiles + tiles_per_split - 1) / tiles_per_split;  // none left empty
   const int len = int(tiles_per_split * kThreads);
   p.split = SplitShape{int(p.sj), len, len};
-  // Long splits: the last quarter of them (at least one) a quarter as long as
-  // the others, so the launch's last round holds short workgroups and drains
-  // quickly (measured at N = 262144, the mixed force in 8 splits: -4.1 %,
-  // where 16 uniform splits gain -2.5 % at twice the partial sums).
-  const int64_t two_level_tiles = 64;
+  // Splits of 8 tiles or more: the last quarter of them (at least one) a
+  // quarter as long as the others, so the launch's last round holds short
+  // workgroups and drains quickly (measured at N = 262144, the mixed force in
+  // 8 splits: -4.1 %, where 16 uniform splits gain -2.5 % at twice the
+  // partial sums; at N = 65536, 32 splits of 8 tiles: -2.4 %).
+  const int64_t two_level_tiles = 8;
   if (tiles_per_split >= two_level_tiles && p.sj >= 2) {
     const int64_t nshort = std::max<int64_t>(1, p.sj / 4), nlong = p.sj - nshort;
     for (int64_t tl = (4 * ntiles + 4 * nlong + nshort - 1) / (4 * nlong + nshort);;
