@@ -213,6 +213,29 @@ def test_vjp_parity_mid_size(B, dev, oracle, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_two_length_splits_ragged(B, dev, oracle, prec):
+    # N = 65027 (254 tiles and 3 bodies): the force and VJP plans take source
+    # splits of two lengths (24 of 10 tiles, then 8 of 2, the last holding
+    # the ragged tile); 256 seeded rows and the last 64 against the oracle,
+    # and the whole-system row range equal to the force bitwise
+    n = 65027
+    say("two-length splits, ragged", prec, n)
+    pos, _, mass = inputs.uniform_cube(n, 615)
+    g = inputs.upstream_normal(n, 616)
+    P, M = T(pos, dev), T(mass, dev)
+    rows = np.union1d(inputs.subset_rows(n, 256, 617), np.arange(n - 64, n))
+    a = N(B.nbody_accel(P, M, 1.0, 1e-3, prec))
+    _check_bound(a[:, rows], oracle.accel_rows(pos, mass, 1.0, 1e-3, rows),
+                 _tol.accel_bound(pos, mass, 1.0, 1e-3, prec, rows), prec)
+    assert np.array_equal(a, N(B.nbody_accel_rows(P, M, 0, n, 1.0, 1e-3, prec)))
+    gx, gm = B.nbody_accel_vjp(P, M, T(g, dev), 1.0, 1e-3, prec)
+    rx, rm = oracle.accel_vjp_rows(pos, mass, g, 1.0, 1e-3, rows)
+    bx, bm = _tol.vjp_bound(pos, mass, g, 1.0, 1e-3, prec, rows)
+    _check_bound(N(gx)[:, rows], rx, bx, prec + " dL/dx")
+    assert np.all(np.abs(N(gm)[rows] - rm) <= bm), prec + " dL/dm"
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_vjp_edge_cases(B, dev, oracle, prec):
     say("vjp edge cases", prec)
     # one body: its only pair is the self pair, which adds nothing
